@@ -1,0 +1,231 @@
+// C ABI: operator setup, apply, diagonal, load vector, errors.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace pa {
+
+static thread_local char g_err[1024] = "";
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int validate_mesh(const pa_mesh_t* m, MeshDesc* out) {
+    if (!m) return fail(PA_EINVAL, "mesh is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (m->n[a] < 1) return fail(PA_EINVAL, "mesh n[%d] = %d must be >= 1", a, m->n[a]);
+    const double* A = m->A;
+    const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                       A[2] * (A[3] * A[7] - A[4] * A[6]);
+    if (!(det > 0.0) || !std::isfinite(det)) return fail(PA_EINVAL, "det(A) = %g must be > 0", det);
+    if (m->clamped_faces >> 6) return fail(PA_EINVAL, "clamped_faces has bits beyond the 6 faces");
+    for (int a = 0; a < 3; ++a) {
+        out->vert[a].resize(m->n[a] + 1);
+        if (m->grade[a]) {
+            for (int i = 0; i <= m->n[a]; ++i) {
+                const double v = m->grade[a][i];
+                if (!std::isfinite(v)) return fail(PA_EINVAL, "grade[%d][%d] is not finite", a, i);
+                if (i > 0 && !(v > m->grade[a][i - 1]))
+                    return fail(PA_EINVAL, "grade[%d] must be strictly increasing", a);
+                out->vert[a][i] = v;
+            }
+        } else {
+            if (!(m->L[a] > 0.0) || !std::isfinite(m->L[a])) return fail(PA_EINVAL, "L[%d] must be > 0", a);
+            for (int i = 0; i <= m->n[a]; ++i) out->vert[a][i] = m->L[a] * (double)i / (double)m->n[a];
+            out->vert[a][m->n[a]] = m->L[a];
+        }
+        out->n[a] = m->n[a];
+        out->x0[a] = m->x0[a];
+    }
+    for (int i = 0; i < 9; ++i) out->A[i] = A[i];
+    out->clamp = m->clamped_faces;
+    return PA_OK;
+}
+
+// Build an operator from a validated mesh description (also used for solver levels).
+int create_op(const MeshDesc& md, int p, int q, const double* lam, const double* mu, int dtype, hipStream_t s,
+              pa_op** out) {
+    if (p < 1) return fail(PA_EINVAL, "p = %d must be >= 1", p);
+    if (p > kMaxP) return fail(PA_EUNSUPPORTED, "p = %d > %d is not built", p, kMaxP);
+    if (q < p + 1 || q > p + 3) return fail(PA_EINVAL, "q = %d must be in [p+1, p+3] = [%d, %d]", q, p + 1, p + 3);
+    if (dtype != PA_F64 && dtype != PA_F32) return fail(PA_EINVAL, "dtype %d is not PA_F64/PA_F32", dtype);
+    const int64_t NE = (int64_t)md.n[0] * md.n[1] * md.n[2];
+    const int64_t Nn = (int64_t)(md.n[0] * (int64_t)p + 1) * (md.n[1] * (int64_t)p + 1) * (md.n[2] * (int64_t)p + 1);
+    if (3 * Nn >= (int64_t(1) << 31) || NE >= (int64_t(1) << 31))
+        return fail(PA_EUNSUPPORTED, "problem too large (%lld dofs): 32-bit indexing", (long long)(3 * Nn));
+    for (int64_t e = 0; e < NE; ++e) {
+        const double l = lam[e], m = mu[e];
+        if (!std::isfinite(l) || !std::isfinite(m) || !(m > 0.0) || !(l + 2.0 * m / 3.0 > 0.0))
+            return fail(PA_EINVAL, "element %lld: need mu > 0 and lambda + 2 mu / 3 > 0 (lambda=%g, mu=%g)",
+                        (long long)e, l, m);
+    }
+    pa_op* op = new (std::nothrow) pa_op();
+    if (!op) return fail(PA_ENOMEM, "host allocation failed");
+    op->mesh = md;
+    op->p = p;
+    op->q = q;
+    op->dtype = dtype;
+    op->NE = NE;
+    op->Nn = Nn;
+    op->N = 3 * Nn;
+    op->stream = s;
+    op->lam.assign(lam, lam + NE);
+    op->mu.assign(mu, mu + NE);
+    pa_solve_opts_default(&op->cached_opts);
+    int rc = PA_OK;
+    double* d_lm = nullptr;
+    const size_t nvert = md.vert[0].size() + md.vert[1].size() + md.vert[2].size();
+    const size_t esz = dtype == PA_F64 ? sizeof(double) : sizeof(float);
+    do {
+        rc = compute_tables(p, q, s, &op->d_tab, &op->tab);
+        if (rc) break;
+        if (hipMalloc(&op->d_vert, nvert * sizeof(double)) != hipSuccess ||
+            hipMalloc(&op->ed, (size_t)NE * kEdStride * esz) != hipSuccess ||
+            hipMalloc(&d_lm, 2 * (size_t)NE * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            rc = fail(PA_ENOMEM, "device allocation failed (%lld elements)", (long long)NE);
+            break;
+        }
+        std::vector<double> hv;
+        hv.reserve(nvert);
+        for (int a = 0; a < 3; ++a) hv.insert(hv.end(), md.vert[a].begin(), md.vert[a].end());
+        hipError_t e = hipMemcpyAsync(op->d_vert, hv.data(), nvert * sizeof(double), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_lm, lam, NE * sizeof(double), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_lm + NE, mu, NE * sizeof(double), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) { rc = fail(PA_EHIP, "upload failed: %s", hipGetErrorString(e)); break; }
+        rc = compute_element_data(md, op->d_vert, d_lm, d_lm + NE, dtype, op->ed, s);
+        if (rc) break;
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { rc = fail(PA_EHIP, "setup failed: %s", hipGetErrorString(e)); break; }
+    } while (0);
+    if (d_lm) (void)hipFree(d_lm);
+    if (rc) {
+        pa_elast_destroy(op);
+        return rc;
+    }
+    *out = op;
+    return PA_OK;
+}
+
+int apply_op(const pa_op* op, const void* x, void* y, int flags) {
+    const bool constrained = !(flags & PA_UNCONSTRAINED);
+    const int add = (flags & PA_ADD) ? 1 : 0;
+    ApplyLaunch L;
+    L.g = make_geom(op->mesh, op->p, constrained);
+    L.x = x;
+    L.y = y;
+    L.ed = op->ed;
+    L.tab = &op->tab;
+    L.add = add;
+    L.stream = op->stream;
+    int rc = launch_apply_prep(x, y, op->dtype, L.g, add, op->stream);
+    if (rc) return rc;
+    const int qo = op->q - op->p - 1;
+    switch (op->p) {
+        case 1: return launch_apply_p1(L, qo, op->dtype);
+        case 2: return launch_apply_p2(L, qo, op->dtype);
+        case 3: return launch_apply_p3(L, qo, op->dtype);
+        case 4: return launch_apply_p4(L, qo, op->dtype);
+        case 5: return launch_apply_p5(L, qo, op->dtype);
+        case 6: return launch_apply_p6(L, qo, op->dtype);
+        case 7: return launch_apply_p7(L, qo, op->dtype);
+        case 8: return launch_apply_p8(L, qo, op->dtype);
+    }
+    return fail(PA_EUNSUPPORTED, "p = %d not built", op->p);
+}
+
+}  // namespace pa
+
+using namespace pa;
+
+extern "C" {
+
+const char* pa_last_error(void) { return g_err; }
+
+void pa_solve_opts_default(pa_solve_opts_t* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->mode = PA_SOLVE_F64;
+    o->stop = PA_STOP_PREC;
+    o->p_levels = -1;
+    o->h_levels = -1;
+    o->cheb_degree = 2;
+    o->power_iters = 10;
+    o->cheb_lo_frac = 0.3;
+    o->cheb_safety = 1.2;
+    o->max_iter = 5000;
+    o->inner_rtol = 1e-4;
+    o->inner_max_iter = 50;
+    o->max_outer = 20;
+    o->seed = 7;
+    o->coarse_max_dofs = 3000;
+    o->lambda_max = nullptr;
+}
+
+int pa_elast_setup(const pa_mesh_t* m, int p, int q, const double* lambda, const double* mu, int dtype,
+                   void* hip_stream, pa_op_t** out) {
+    if (!out) return fail(PA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!lambda || !mu) return fail(PA_EINVAL, "lambda/mu is NULL");
+    MeshDesc md;
+    int rc = validate_mesh(m, &md);
+    if (rc) return rc;
+    return create_op(md, p, q, lambda, mu, dtype, (hipStream_t)hip_stream, out);
+}
+
+void pa_elast_destroy(pa_op_t* op) {
+    if (!op) return;
+    if (op->cached) gmg_destroy(op->cached);
+    if (op->ed) (void)hipFree(op->ed);
+    if (op->d_tab) (void)hipFree(op->d_tab);
+    if (op->d_vert) (void)hipFree(op->d_vert);
+    delete op;
+}
+
+int pa_elast_set_stream(pa_op_t* op, void* hip_stream) {
+    if (!op) return fail(PA_EINVAL, "op is NULL");
+    op->stream = (hipStream_t)hip_stream;
+    return PA_OK;
+}
+
+int pa_elast_ndofs(const pa_op_t* op, int64_t* n) {
+    if (!op || !n) return fail(PA_EINVAL, "NULL argument");
+    *n = op->N;
+    return PA_OK;
+}
+
+int pa_elast_apply_ex(pa_op_t* op, const void* x, void* y, int flags) {
+    if (!op || !x || !y) return fail(PA_EINVAL, "NULL argument");
+    if (x == y) return fail(PA_EINVAL, "x and y must not alias");
+    if (flags & ~(PA_UNCONSTRAINED | PA_ADD)) return fail(PA_EINVAL, "unknown flags 0x%x", flags);
+    return apply_op(op, x, y, flags);
+}
+
+int pa_elast_apply(pa_op_t* op, const void* x, void* y) { return pa_elast_apply_ex(op, x, y, 0); }
+
+int pa_elast_diagonal(pa_op_t* op, void* d, int flags) {
+    if (!op || !d) return fail(PA_EINVAL, "NULL argument");
+    if (flags & ~PA_UNCONSTRAINED) return fail(PA_EINVAL, "unknown flags 0x%x", flags);
+    return launch_diagonal(op, d, (flags & PA_UNCONSTRAINED) ? 0 : 1);
+}
+
+int pa_elast_rhs(pa_op_t* op, const double f[3], int traction_face, const double t[3], double* b) {
+    if (!op || !b) return fail(PA_EINVAL, "NULL argument");
+    if (traction_face < -1 || traction_face > 5) return fail(PA_EINVAL, "traction_face %d", traction_face);
+    if (traction_face >= 0 && !t) return fail(PA_EINVAL, "traction vector is NULL");
+    return launch_rhs(op, f, traction_face, t, b, op->d_vert);
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// Internal declarations of the paelast HIP library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "paelast.h"
+
+namespace pa {
+
+constexpr int kMaxP = 8;
+constexpr int kMaxD = kMaxP + 1;
+constexpr int kMaxQ = kMaxP + 3;
+constexpr int kEdStride = 12;   // words of per-element PA data: J^{-1} (9), detJ*lambda, detJ*mu, pad
+
+// Thread-local error message; returns `code` for convenient `return fail(...)`.
+int fail(int code, const char* fmt, ...);
+
+#define PA_HIP(call)                                                                 \
+    do {                                                                             \
+        hipError_t _e = (call);                                                      \
+        if (_e != hipSuccess) return ::pa::fail(PA_EHIP, "%s failed: %s", #call,   \
+                                                hipGetErrorString(_e));             \
+    } while (0)
+
+// Host copy of the 1D tables on [0,1]: B[i*q+k] = l_i(x_k), G[i*q+k] = l_i'(x_k), w[k].
+struct Tables {
+    int p = 0, q = 0;
+    double gll[kMaxD];
+    double xq[kMaxQ];
+    double B[kMaxD * kMaxQ];
+    double G[kMaxD * kMaxQ];
+    double w[kMaxQ];
+};
+
+struct MeshDesc {
+    int n[3] = {0, 0, 0};
+    double A[9];
+    double x0[3];
+    uint32_t clamp = 0;
+    std::vector<double> vert[3];   // vertex coordinates per axis (n[a]+1)
+};
+
+// Geometry of one operator as the kernels see it.
+struct Geom {
+    int nx, ny, nz;     // elements per axis
+    int Nx, Ny, Nz;     // nodes per axis (n*p+1)
+    int Nn;             // nodes
+    int NE;             // elements
+    uint32_t clamp;     // clamped-face mask (0: unconstrained)
+};
+
+struct ApplyLaunch {
+    Geom g;
+    const void* x;
+    void* y;
+    const void* ed;      // per-element data of the launch dtype
+    const Tables* tab;
+    int add;             // accumulate into y (y pre-initialised by the caller)
+    hipStream_t stream;
+};
+
+// Fused apply launchers, one translation unit per degree p.  q_off = q - p - 1.
+int launch_apply_p1(const ApplyLaunch&, int q_off, int dtype);
+int launch_apply_p2(const ApplyLaunch&, int q_off, int dtype);
+int launch_apply_p3(const ApplyLaunch&, int q_off, int dtype);
+int launch_apply_p4(const ApplyLaunch&, int q_off, int dtype);
+int launch_apply_p5(const ApplyLaunch&, int q_off, int dtype);
+int launch_apply_p6(const ApplyLaunch&, int q_off, int dtype);
+int launch_apply_p7(const ApplyLaunch&, int q_off, int dtype);
+int launch_apply_p8(const ApplyLaunch&, int q_off, int dtype);
+
+inline Geom make_geom(const MeshDesc& m, int p, bool constrained) {
+    Geom g;
+    g.nx = m.n[0]; g.ny = m.n[1]; g.nz = m.n[2];
+    g.Nx = g.nx * p + 1; g.Ny = g.ny * p + 1; g.Nz = g.nz * p + 1;
+    g.Nn = g.Nx * g.Ny * g.Nz;
+    g.NE = g.nx * g.ny * g.nz;
+    g.clamp = constrained ? m.clamp : 0u;
+    return g;
+}
+
+}  // namespace pa
+
+// Opaque handles of the C ABI.
+struct pa_op {
+    pa::MeshDesc mesh;
+    int p = 0, q = 0, dtype = PA_F64;
+    int64_t NE = 0, Nn = 0, N = 0;
+    hipStream_t stream = nullptr;
+    std::vector<double> lam, mu;     // host copies (used to build solver hierarchies)
+    void* ed = nullptr;              // device per-element data [NE][kEdStride] of dtype
+    double* d_tab = nullptr;         // device copy of the FP64 tables (B, G, w, bb/bg/gg, sB)
+    double* d_vert = nullptr;        // device vertex coordinates, x | y | z
+    pa::Tables tab;                  // host copy of the tables (kernel arguments)
+    pa_gmg* cached = nullptr;        // hierarchy cached by gmg_pcg_solve
+    pa_solve_opts_t cached_opts;
+};

@@ -1,0 +1,33 @@
+// Device helpers and host launchers shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace pa {
+
+__device__ __forceinline__ bool clamped_node(uint32_t m, int gx, int gy, int gz, const Geom& g) {
+    return ((m & 1u) && gx == 0) || ((m & 2u) && gx == g.Nx - 1) || ((m & 4u) && gy == 0) ||
+           ((m & 8u) && gy == g.Ny - 1) || ((m & 16u) && gz == 0) || ((m & 32u) && gz == g.Nz - 1);
+}
+
+// setup.hip
+int tables_words(int p, int q);
+int compute_tables(int p, int q, hipStream_t s, double** d_tab, Tables* host);
+int compute_element_data(const MeshDesc& m, const double* d_vert, const double* d_lam, const double* d_mu,
+                         int dtype, void* ed, hipStream_t s);
+int launch_diagonal(const pa_op* op, void* d, int constrained);
+int launch_rhs(const pa_op* op, const double f[3], int face, const double t[3], double* b, const double* d_vert);
+
+// vec.hip
+int launch_fill(void* y, int dtype, int64_t n, double v, hipStream_t s);
+int launch_set_clamped(void* y, int dtype, const Geom& g, double v, hipStream_t s);
+// Before the element kernel: y = 0 (add == 0) on free dofs; clamped dofs get y = x
+// (add == 0) or y += x (add != 0).  With add != 0 and no clamp nothing is launched.
+int launch_apply_prep(const void* x, void* y, int dtype, const Geom& g, int add, hipStream_t s);
+
+// apply dispatch (api.hip)
+int apply_op(const pa_op* op, const void* x, void* y, int flags);
+
+}  // namespace pa
