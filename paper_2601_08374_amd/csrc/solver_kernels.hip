@@ -1,0 +1,840 @@
+// Streaming kernels of the solver: reductions with FP64 accumulation, PCG and
+// Chebyshev vector updates, casts, p/h transfers, coarse-matrix assembly and
+// inversion, SplitMix64 start vectors.  All of them are HBM-bound except the
+// coarse assembly/inversion (setup only).
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "kernels.h"
+#include "solver.h"
+
+namespace pa {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline int grid_for(int64_t n) {
+    int64_t b = (n + kBlock - 1) / kBlock;
+    if (b > 65536) b = 65536;
+    return (int)(b < 1 ? 1 : b);
+}
+
+#define GRID_STRIDE(i, n) \
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+// ---------------------------------------------------------------- reductions
+// Stage 1: every block reduces a fixed grid-stride slice in FP64 (fixed grid ->
+// deterministic); stage 2 (one block) sums the partials in a fixed order and
+// then runs the scalar logic of the caller (alpha, beta, convergence test).
+template <typename TA, typename TB>
+__global__ void dot_partial_kernel(const TA* __restrict__ a, const TB* __restrict__ b, const TB* __restrict__ c,
+                                   int64_t n, double* __restrict__ part) {
+    // part[blk] = sum a*b ; if c: part[gridDim + blk] = sum a*a (second product)
+    __shared__ double s0[kBlock], s1[kBlock];
+    double acc0 = 0.0, acc1 = 0.0;
+    GRID_STRIDE(i, n) {
+        const double av = (double)a[i];
+        acc0 += av * (double)b[i];
+        if (c) acc1 += av * av;
+    }
+    s0[threadIdx.x] = acc0;
+    s1[threadIdx.x] = acc1;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s0[threadIdx.x] += s0[threadIdx.x + w];
+            s1[threadIdx.x] += s1[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = s0[0];
+        part[gridDim.x + blockIdx.x] = s1[0];
+    }
+}
+
+__device__ double block_sum(const double* part, int np, double* sh) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) acc += part[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// PCG scalar logic, run by thread 0 after the sums are known.
+//   op = FIN_STORE : s[slot] = sum0
+//   op = FIN_ALPHA : s[PAP] = sum0; alpha = rz/pAp unless done; breakdown if pAp <= 0 or NaN
+//   op = FIN_BETA  : rz_new = sum0 (r.z), rr = sum1 (r.r); convergence test; beta = rz_new/rz; rz = rz_new
+__global__ void dot_final_kernel(const double* __restrict__ part, int np, double* __restrict__ s, int op, int slot) {
+    __shared__ double sh[kBlock];
+    const double s0 = block_sum(part, np, sh);
+    const double s1 = block_sum(part + np, np, sh);
+    if (threadIdx.x != 0) return;
+    if (op == FIN_STORE) {
+        s[slot] = s0;
+        s[slot + 1] = s1;
+        return;
+    }
+    if (s[S_DONE] != 0.0) return;
+    if (op == FIN_ALPHA) {
+        s[S_PAP] = s0;
+        if (!(s0 > 0.0) || s0 != s0) {
+            s[S_DONE] = 2.0;   // breakdown
+            s[S_ALPHA] = 0.0;
+            return;
+        }
+        s[S_ALPHA] = s[S_RZ] / s0;
+        return;
+    }
+    // FIN_BETA
+    const double rz_new = s0, rr = s1;
+    s[S_ITERS] += 1.0;
+    const bool prec = s[S_STOP] == 0.0;
+    const double crit = prec ? sqrt(fabs(rz_new) / s[S_RZ0]) : sqrt(rr / s[S_BB]);
+    s[S_CRIT] = crit;
+    s[S_RRLAST] = rr;
+    if (rz_new != rz_new || rr != rr) {
+        s[S_DONE] = 2.0;
+        return;
+    }
+    if (crit <= s[S_RTOL]) {
+        s[S_DONE] = 1.0;
+        s[S_BETA] = 0.0;
+        return;
+    }
+    s[S_BETA] = rz_new / s[S_RZ];
+    s[S_RZ] = rz_new;
+}
+
+// After the first preconditioner application: rz = rz0 = r.z, rr0 = r.r.
+__global__ void pcg_init_scalars_kernel(const double* __restrict__ part, int np, double* __restrict__ s,
+                                        double rtol, int stop) {
+    __shared__ double sh[kBlock];
+    const double s0 = block_sum(part, np, sh);
+    const double s1 = block_sum(part + np, np, sh);
+    if (threadIdx.x != 0) return;
+    s[S_RZ] = s0;
+    s[S_RZ0] = s0 > 0.0 ? s0 : 1.0;
+    s[S_RTOL] = rtol;
+    s[S_STOP] = (double)stop;
+    s[S_ITERS] = 0.0;
+    s[S_DONE] = 0.0;
+    s[S_ALPHA] = 0.0;
+    s[S_BETA] = 0.0;
+    s[S_RRLAST] = s1;
+    const bool prec = stop == 0;
+    const double crit = prec ? 1.0 : sqrt(s1 / s[S_BB]);
+    s[S_CRIT] = crit;
+    if (s0 == 0.0 || (!prec && crit <= rtol) || s1 == 0.0) s[S_DONE] = 1.0;   // already solved
+}
+
+// ---------------------------------------------------------------- PCG updates
+template <typename T>
+__global__ void pcg_xr_kernel(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ Ap,
+                              const double* __restrict__ s, int64_t n) {
+    if (s[S_DONE] != 0.0) return;
+    const T a = (T)s[S_ALPHA];
+    GRID_STRIDE(i, n) {
+        x[i] += a * p[i];
+        r[i] -= a * Ap[i];
+    }
+}
+
+template <typename T>
+__global__ void pcg_p_kernel(T* __restrict__ p, const T* __restrict__ z, const double* __restrict__ s, int64_t n) {
+    if (s[S_DONE] != 0.0) return;
+    const T b = (T)s[S_BETA];
+    GRID_STRIDE(i, n) p[i] = z[i] + b * p[i];
+}
+
+// ---------------------------------------------------------------- generic vector ops
+template <typename T>
+__global__ void axpby_kernel(T* __restrict__ y, const T* __restrict__ x, double a, double b, int64_t n) {
+    // y = a*x + b*y
+    const T ta = (T)a, tb = (T)b;
+    GRID_STRIDE(i, n) y[i] = ta * x[i] + tb * y[i];
+}
+
+template <typename T>
+__global__ void residual_kernel(T* __restrict__ r, const T* __restrict__ b, const T* __restrict__ Ax, int64_t n) {
+    GRID_STRIDE(i, n) r[i] = b[i] - Ax[i];
+}
+
+template <typename T>
+__global__ void copy_kernel(T* __restrict__ y, const T* __restrict__ x, int64_t n) {
+    GRID_STRIDE(i, n) y[i] = x[i];
+}
+
+template <typename TO, typename TI>
+__global__ void cast_scale_kernel(TO* __restrict__ y, const TI* __restrict__ x, const double* __restrict__ s, int slot,
+                                  int inv_sqrt, int64_t n) {
+    // y = x * f, f = 1/sqrt(s[slot]) (inv_sqrt) or sqrt(s[slot]) (!inv_sqrt)
+    const double v = s[slot];
+    const double f = inv_sqrt ? (v > 0.0 ? 1.0 / sqrt(v) : 0.0) : sqrt(v);
+    GRID_STRIDE(i, n) y[i] = (TO)((double)x[i] * f);
+}
+
+template <typename TI>
+__global__ void ir_update_kernel(double* __restrict__ x, const TI* __restrict__ d, const double* __restrict__ s,
+                                 int slot, int64_t n) {
+    // x += sqrt(s[slot]) * d   (the correction was solved for the unit-norm residual)
+    const double f = sqrt(s[slot]);
+    GRID_STRIDE(i, n) x[i] += f * (double)d[i];
+}
+
+// Chebyshev step: x += d; r -= t; d = c1*d + c2*dinv*r
+template <typename T>
+__global__ void cheb_step_kernel(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ t, T* __restrict__ d,
+                                 const T* __restrict__ dinv, double c1, double c2, int64_t n) {
+    const T a = (T)c1, b = (T)c2;
+    GRID_STRIDE(i, n) {
+        const T dv = d[i];
+        x[i] += dv;
+        const T rv = r[i] - t[i];
+        r[i] = rv;
+        d[i] = a * dv + b * dinv[i] * rv;
+    }
+}
+
+// d = c * dinv * r ; optionally x = d (x_set) or x += d (x_add)
+template <typename T>
+__global__ void cheb_first_kernel(T* __restrict__ d, const T* __restrict__ dinv, const T* __restrict__ r, double c,
+                                  int64_t n) {
+    const T tc = (T)c;
+    GRID_STRIDE(i, n) d[i] = tc * dinv[i] * r[i];
+}
+
+template <typename T>
+__global__ void add_kernel(T* __restrict__ y, const T* __restrict__ x, int64_t n) {
+    GRID_STRIDE(i, n) y[i] += x[i];
+}
+
+template <typename T>
+__global__ void reciprocal_kernel(T* __restrict__ y, int64_t n) {
+    GRID_STRIDE(i, n) y[i] = T(1) / y[i];
+}
+
+// v[i] = 2u-1 from the (i+1)-th output of SplitMix64 seeded with `seed` (Steele-Lea-Flood / Vigna).
+template <typename T>
+__global__ void splitmix_kernel(T* __restrict__ v, uint64_t seed, int64_t n) {
+    GRID_STRIDE(i, n) {
+        uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z = z ^ (z >> 31);
+        v[i] = (T)(2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0);
+    }
+}
+
+// Weighted dot sum v_i^2 / dinv_i (= v.Dv) into part (stage 1)
+template <typename T>
+__global__ void vdv_partial_kernel(const T* __restrict__ v, const T* __restrict__ dinv, int64_t n,
+                                   double* __restrict__ part) {
+    __shared__ double s0[kBlock];
+    double acc = 0.0;
+    GRID_STRIDE(i, n) {
+        const double a = (double)v[i];
+        acc += a * a / (double)dinv[i];
+    }
+    s0[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s0[threadIdx.x] += s0[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = s0[0];
+        part[gridDim.x + blockIdx.x] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------- p-transfer
+// Per element, fine nodal values = (I (x) I (x) I) coarse nodal values with
+// I[i][j] = l^c_j(xi^f_i) (coarse Lagrange basis at the fine Gauss-Lobatto nodes).
+// A fine node is written only by its owner element (local index < pf, or the last
+// element of the axis), so prolongation is deterministic and race-free.
+// Restriction is the exact transpose: each element contracts the owned entries of
+// the fine vector with I^T and scatter-adds into the coarse vector.
+__device__ __forceinline__ bool owns(int e, int i, int n, int p) { return i < p || e == n - 1; }
+
+template <typename T>
+__global__ void p_prolong_kernel(const T* __restrict__ xc, T* __restrict__ xf, const double* __restrict__ I, int pc,
+                                 int pf, Geom gc, Geom gf, int add) {
+    extern __shared__ double sm[];
+    const int Dc = pc + 1, Df = pf + 1;
+    const int Dc3 = Dc * Dc * Dc;
+    double* X = sm;                         // [3][Dc][Dc][Dc]
+    double* T1 = X + 3 * Dc3;               // [3][Dc][Dc][Df]
+    double* T2 = T1 + 3 * Dc * Dc * Df;     // [3][Dc][Df][Df]
+    double* Is = T2 + 3 * Dc * Df * Df;     // [Df][Dc]
+    const int e = blockIdx.x;
+    const int ex = e % gf.nx, ey = (e / gf.nx) % gf.ny, ez = e / (gf.nx * gf.ny);
+    for (int w = threadIdx.x; w < Df * Dc; w += blockDim.x) Is[w] = I[w];
+    for (int w = threadIdx.x; w < 3 * Dc3; w += blockDim.x) {
+        const int c = w / Dc3, a = w % Dc3;
+        const int ix = a % Dc, iy = (a / Dc) % Dc, iz = a / (Dc * Dc);
+        const int node = (ex * pc + ix) + gc.Nx * ((ey * pc + iy) + gc.Ny * (ez * pc + iz));
+        X[w] = (double)xc[(size_t)c * gc.Nn + node];
+    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < 3 * Dc * Dc * Df; w += blockDim.x) {
+        const int i = w % Df, r = w / Df;   // r = (c, jz, jy)
+        double acc = 0.0;
+        for (int j = 0; j < Dc; ++j) acc += Is[i * Dc + j] * X[r * Dc + j];
+        T1[w] = acc;
+    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < 3 * Dc * Df * Df; w += blockDim.x) {
+        const int ixf = w % Df, iyf = (w / Df) % Df, r = w / (Df * Df);   // r = (c, jz)
+        double acc = 0.0;
+        for (int j = 0; j < Dc; ++j) acc += Is[iyf * Dc + j] * T1[(r * Dc + j) * Df + ixf];
+        T2[w] = acc;
+    }
+    __syncthreads();
+    const int Df3 = Df * Df * Df;
+    for (int w = threadIdx.x; w < 3 * Df3; w += blockDim.x) {
+        const int c = w / Df3, a = w % Df3;
+        const int ix = a % Df, iy = (a / Df) % Df, iz = a / (Df * Df);
+        if (!owns(ex, ix, gf.nx, pf) || !owns(ey, iy, gf.ny, pf) || !owns(ez, iz, gf.nz, pf)) continue;
+        const int gx = ex * pf + ix, gy = ey * pf + iy, gz = ez * pf + iz;
+        double acc = 0.0;
+        for (int j = 0; j < Dc; ++j) acc += Is[iz * Dc + j] * T2[((c * Dc + j) * Df + iy) * Df + ix];
+        const size_t o = (size_t)c * gf.Nn + gx + gf.Nx * (gy + gf.Ny * gz);
+        if (clamped_node(gf.clamp, gx, gy, gz, gf)) {
+            if (!add) xf[o] = T(0);
+        } else {
+            xf[o] = add ? xf[o] + (T)acc : (T)acc;
+        }
+    }
+}
+
+template <typename T>
+__global__ void p_restrict_kernel(const T* __restrict__ rf, T* __restrict__ rc, const double* __restrict__ I, int pc,
+                                  int pf, Geom gc, Geom gf) {
+    extern __shared__ double sm[];
+    const int Dc = pc + 1, Df = pf + 1;
+    const int Df3 = Df * Df * Df;
+    double* X = sm;                          // [3][Df][Df][Df] owned fine values
+    double* T1 = X + 3 * Df3;                // [3][Df][Df][Dc]  (z, y fine; x coarse)
+    double* T2 = T1 + 3 * Df * Df * Dc;      // [3][Df][Dc][Dc]
+    double* Is = T2 + 3 * Df * Dc * Dc;      // [Df][Dc]
+    const int e = blockIdx.x;
+    const int ex = e % gf.nx, ey = (e / gf.nx) % gf.ny, ez = e / (gf.nx * gf.ny);
+    for (int w = threadIdx.x; w < Df * Dc; w += blockDim.x) Is[w] = I[w];
+    for (int w = threadIdx.x; w < 3 * Df3; w += blockDim.x) {
+        const int c = w / Df3, a = w % Df3;
+        const int ix = a % Df, iy = (a / Df) % Df, iz = a / (Df * Df);
+        double v = 0.0;
+        if (owns(ex, ix, gf.nx, pf) && owns(ey, iy, gf.ny, pf) && owns(ez, iz, gf.nz, pf)) {
+            const int node = (ex * pf + ix) + gf.Nx * ((ey * pf + iy) + gf.Ny * (ez * pf + iz));
+            v = (double)rf[(size_t)c * gf.Nn + node];
+        }
+        X[w] = v;
+    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < 3 * Df * Df * Dc; w += blockDim.x) {
+        const int j = w % Dc, r = w / Dc;   // r = (c, iz, iy)
+        double acc = 0.0;
+        for (int i = 0; i < Df; ++i) acc += Is[i * Dc + j] * X[r * Df + i];
+        T1[w] = acc;
+    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < 3 * Df * Dc * Dc; w += blockDim.x) {
+        const int jx = w % Dc, jy = (w / Dc) % Dc, r = w / (Dc * Dc);   // r = (c, iz)
+        double acc = 0.0;
+        for (int i = 0; i < Df; ++i) acc += Is[i * Dc + jy] * T1[(r * Df + i) * Dc + jx];
+        T2[w] = acc;
+    }
+    __syncthreads();
+    const int Dc3 = Dc * Dc * Dc;
+    for (int w = threadIdx.x; w < 3 * Dc3; w += blockDim.x) {
+        const int c = w / Dc3, a = w % Dc3;
+        const int jx = a % Dc, jy = (a / Dc) % Dc, jz = a / (Dc * Dc);
+        double acc = 0.0;
+        for (int i = 0; i < Df; ++i) acc += Is[i * Dc + jz] * T2[((c * Df + i) * Dc + jy) * Dc + jx];
+        const int gx = ex * pc + jx, gy = ey * pc + jy, gz = ez * pc + jz;
+        if (clamped_node(gc.clamp, gx, gy, gz, gc)) continue;
+        unsafeAtomicAdd(rc + (size_t)c * gc.Nn + gx + gc.Nx * (gy + gc.Ny * gz), (T)acc);
+    }
+}
+
+// I[i][j] = l^c_j(xi^f_i) from the two sets of Gauss-Lobatto nodes
+__global__ void p_interp_matrix_kernel(const double* __restrict__ gll_c, const double* __restrict__ gll_f, int pc,
+                                       int pf, double* __restrict__ I) {
+    const int Dc = pc + 1, Df = pf + 1;
+    const int w = threadIdx.x;
+    if (w >= Df * Dc) return;
+    const int i = w / Dc, j = w % Dc;
+    const double x = gll_f[i];
+    double v = 1.0;
+    for (int m = 0; m < Dc; ++m)
+        if (m != j) v *= (x - gll_c[m]) / (gll_c[j] - gll_c[m]);
+    I[w] = v;
+}
+
+// ---------------------------------------------------------------- h-transfer (p = 1)
+// Per axis: fine vertex g takes coarse vertices i0[g], i1[g] with weights 1-t[g], t[g];
+// the transpose lists, for coarse vertex j, up to 3 fine vertices fi[j][k] with fw[j][k].
+template <typename T>
+__global__ void h_prolong_kernel(const T* __restrict__ xc, T* __restrict__ xf, HAxis ax, HAxis ay, HAxis az, Geom gc,
+                                 Geom gf, int add) {
+    GRID_STRIDE(node, (int64_t)gf.Nn) {
+        const int gx = (int)(node % gf.Nx), gy = (int)((node / gf.Nx) % gf.Ny), gz = (int)(node / ((int64_t)gf.Nx * gf.Ny));
+        const bool cl = clamped_node(gf.clamp, gx, gy, gz, gf);
+        const int xs[2] = {ax.i0[gx], ax.i1[gx]}, ys[2] = {ay.i0[gy], ay.i1[gy]}, zs[2] = {az.i0[gz], az.i1[gz]};
+        const double wx[2] = {1.0 - ax.t[gx], ax.t[gx]}, wy[2] = {1.0 - ay.t[gy], ay.t[gy]},
+                     wz[2] = {1.0 - az.t[gz], az.t[gz]};
+        for (int c = 0; c < 3; ++c) {
+            double acc = 0.0;
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b)
+                    for (int d = 0; d < 2; ++d) {
+                        const double w = wx[d] * wy[b] * wz[a];
+                        if (w != 0.0)
+                            acc += w * (double)xc[(size_t)c * gc.Nn + xs[d] + gc.Nx * (ys[b] + gc.Ny * zs[a])];
+                    }
+            const size_t o = (size_t)c * gf.Nn + node;
+            if (cl) {
+                if (!add) xf[o] = T(0);
+            } else {
+                xf[o] = add ? xf[o] + (T)acc : (T)acc;
+            }
+        }
+    }
+}
+
+template <typename T>
+__global__ void h_restrict_kernel(const T* __restrict__ rf, T* __restrict__ rc, HAxis ax, HAxis ay, HAxis az, Geom gc,
+                                  Geom gf) {
+    GRID_STRIDE(node, (int64_t)gc.Nn) {
+        const int jx = (int)(node % gc.Nx), jy = (int)((node / gc.Nx) % gc.Ny), jz = (int)(node / ((int64_t)gc.Nx * gc.Ny));
+        const bool cl = clamped_node(gc.clamp, jx, jy, jz, gc);
+        for (int c = 0; c < 3; ++c) {
+            double acc = 0.0;
+            if (!cl) {
+                for (int a = 0; a < 3; ++a) {
+                    const double wz = az.fw[jz * 3 + a];
+                    if (wz == 0.0) continue;
+                    for (int b = 0; b < 3; ++b) {
+                        const double wy = ay.fw[jy * 3 + b];
+                        if (wy == 0.0) continue;
+                        for (int d = 0; d < 3; ++d) {
+                            const double wx = ax.fw[jx * 3 + d];
+                            if (wx == 0.0) continue;
+                            acc += wx * wy * wz *
+                                   (double)rf[(size_t)c * gf.Nn + ax.fi[jx * 3 + d] +
+                                              gf.Nx * (ay.fi[jy * 3 + b] + gf.Ny * az.fi[jz * 3 + a])];
+                        }
+                    }
+                }
+            }
+            rc[(size_t)c * gc.Nn + node] = (T)acc;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- coarse matrix
+// Dense assembly of the constrained operator of a (small) level:
+// K[(c,a),(d,b)] = detJ lambda P_cd + detJ mu (delta_cd tr P + P_dc), P = J^{-T} M(a,b) J^{-1},
+// M_mn(a,b) = prod over directions of 1D integrals sum_k w_k F(i_a,k) F'(i_b,k), F = G in
+// direction m (resp. n) and B otherwise.  One thread per (element, a, b).
+template <typename T>
+__global__ void coarse_assemble_kernel(double* __restrict__ A, int N, const T* __restrict__ ed,
+                                       const double* __restrict__ tab, int p, int q, Geom g) {
+    const int D = p + 1, D3 = D * D * D;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)g.NE * D3 * D3) return;
+    const int e = (int)(t / ((long long)D3 * D3));
+    const int ab = (int)(t % ((long long)D3 * D3));
+    const int a = ab / D3, b = ab % D3;
+    const double* w = tab + D + q;
+    const double* Bt = w + q;
+    const double* Gt = Bt + D * q;
+    const int ia[3] = {a % D, (a / D) % D, a / (D * D)};
+    const int ib[3] = {b % D, (b / D) % D, b / (D * D)};
+    double M[3][3];
+    for (int m = 0; m < 3; ++m)
+        for (int n = 0; n < 3; ++n) {
+            double f = 1.0;
+            for (int d = 0; d < 3; ++d) {
+                const double* Fa = (m == d) ? Gt : Bt;
+                const double* Fb = (n == d) ? Gt : Bt;
+                double s = 0.0;
+                for (int k = 0; k < q; ++k) s += w[k] * Fa[ia[d] * q + k] * Fb[ib[d] * q + k];
+                f *= s;
+            }
+            M[m][n] = f;
+        }
+    const T* o = ed + (size_t)e * kEdStride;
+    double Ji[9];
+    for (int k = 0; k < 9; ++k) Ji[k] = (double)o[k];
+    double P[3][3];
+    for (int c = 0; c < 3; ++c)
+        for (int d = 0; d < 3; ++d) {
+            double s = 0.0;
+            for (int m = 0; m < 3; ++m)
+                for (int n = 0; n < 3; ++n) s += Ji[m * 3 + c] * M[m][n] * Ji[n * 3 + d];
+            P[c][d] = s;
+        }
+    const double tr = P[0][0] + P[1][1] + P[2][2];
+    const double lw = (double)o[9], mw = (double)o[10];
+    const int ex = e % g.nx, ey = (e / g.nx) % g.ny, ez = e / (g.nx * g.ny);
+    const int na = (ex * p + ia[0]) + g.Nx * ((ey * p + ia[1]) + g.Ny * (ez * p + ia[2]));
+    const int nb = (ex * p + ib[0]) + g.Nx * ((ey * p + ib[1]) + g.Ny * (ez * p + ib[2]));
+    for (int c = 0; c < 3; ++c)
+        for (int d = 0; d < 3; ++d) {
+            const double v = lw * P[c][d] + mw * ((c == d ? tr : 0.0) + P[d][c]);
+            unsafeAtomicAdd(A + (size_t)(c * g.Nn + na) * N + (d * g.Nn + nb), v);
+        }
+}
+
+__global__ void coarse_constrain_kernel(double* __restrict__ A, int N, Geom g) {
+    GRID_STRIDE(t, (int64_t)N * N) {
+        const int i = (int)(t / N), j = (int)(t % N);
+        const int ni = i % g.Nn, nj = j % g.Nn;
+        const bool ci = clamped_node(g.clamp, ni % g.Nx, (ni / g.Nx) % g.Ny, ni / (g.Nx * g.Ny), g);
+        const bool cj = clamped_node(g.clamp, nj % g.Nx, (nj / g.Nx) % g.Ny, nj / (g.Nx * g.Ny), g);
+        if (ci || cj) A[t] = (i == j) ? 1.0 : 0.0;
+    }
+}
+
+// Gauss-Jordan elimination step k on [A | X] stored in place (A becomes A^{-1}):
+// the SPD coarse matrix needs no pivoting.  Two kernels per step: scale the pivot
+// row (with the saved pivot column), then eliminate the other rows.
+__global__ void gj_save_col_kernel(const double* __restrict__ A, double* __restrict__ col, int N, int k) {
+    GRID_STRIDE(i, (int64_t)N) col[i] = A[(size_t)i * N + k];
+}
+
+__global__ void gj_update_kernel(double* __restrict__ A, const double* __restrict__ col, int N, int k) {
+    // new row k: A[k][j] / piv (A[k][k] <- 1/piv); other rows: A[i][j] - col[i] * newrow[j]
+    const double piv = col[k];
+    GRID_STRIDE(t, (int64_t)N * N) {
+        const int i = (int)(t / N), j = (int)(t % N);
+        const double akj = (j == k) ? 1.0 / piv : A[(size_t)k * N + j] / piv;
+        if (i == k) continue;
+        const double aik = col[i];
+        const double aij = (j == k) ? 0.0 : A[t];
+        A[t] = aij - aik * akj;
+    }
+}
+
+__global__ void gj_pivot_row_kernel(double* __restrict__ A, const double* __restrict__ col, int N, int k) {
+    const double piv = col[k];
+    GRID_STRIDE(j, (int64_t)N) A[(size_t)k * N + j] = (j == k) ? 1.0 / piv : A[(size_t)k * N + j] / piv;
+}
+
+template <typename T>
+__global__ void dense_cast_kernel(T* __restrict__ out, const double* __restrict__ in, int64_t n) {
+    GRID_STRIDE(i, n) out[i] = (T)in[i];
+}
+
+// y = Ainv x (dense, one wavefront per row, FP64 accumulation)
+template <typename T>
+__global__ void dense_matvec_kernel(const T* __restrict__ Ai, const T* __restrict__ x, T* __restrict__ y, int N) {
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    if (row >= N) return;
+    double acc = 0.0;
+    for (int j = lane; j < N; j += 64) acc += (double)Ai[(size_t)row * N + j] * (double)x[j];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if (lane == 0) y[row] = (T)acc;
+}
+
+}  // namespace
+
+// ============================================================ host launchers
+
+template <typename T> static inline const T* cp(const void* p) { return (const T*)p; }
+template <typename T> static inline T* mp(void* p) { return (T*)p; }
+
+#define PA_CHECK_LAUNCH() PA_HIP(hipGetLastError())
+
+int launch_dot(const void* a, const void* b, const void* c, int dtype, int64_t n, double* part, hipStream_t s) {
+    if (dtype == PA_F64)
+        hipLaunchKernelGGL((dot_partial_kernel<double, double>), dim3(kReduceBlocks), dim3(kBlock), 0, s,
+                           cp<double>(a), cp<double>(b), cp<double>(c), n, part);
+    else
+        hipLaunchKernelGGL((dot_partial_kernel<float, float>), dim3(kReduceBlocks), dim3(kBlock), 0, s,
+                           cp<float>(a), cp<float>(b), cp<float>(c), n, part);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_dot_final(const double* part, double* scal, int op, int slot, hipStream_t s) {
+    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kBlock), 0, s, part, kReduceBlocks, scal, op, slot);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_pcg_init(const double* part, double* scal, double rtol, int stop, hipStream_t s) {
+    hipLaunchKernelGGL(pcg_init_scalars_kernel, dim3(1), dim3(kBlock), 0, s, part, kReduceBlocks, scal, rtol, stop);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_vdv(const void* v, const void* dinv, int dtype, int64_t n, double* part, hipStream_t s) {
+    if (dtype == PA_F64)
+        hipLaunchKernelGGL(vdv_partial_kernel<double>, dim3(kReduceBlocks), dim3(kBlock), 0, s, cp<double>(v),
+                           cp<double>(dinv), n, part);
+    else
+        hipLaunchKernelGGL(vdv_partial_kernel<float>, dim3(kReduceBlocks), dim3(kBlock), 0, s, cp<float>(v),
+                           cp<float>(dinv), n, part);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_pcg_xr(void* x, void* r, const void* p, const void* Ap, const double* sc, int dtype, int64_t n,
+                  hipStream_t s) {
+    if (dtype == PA_F64)
+        hipLaunchKernelGGL(pcg_xr_kernel<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<double>(x), mp<double>(r),
+                           cp<double>(p), cp<double>(Ap), sc, n);
+    else
+        hipLaunchKernelGGL(pcg_xr_kernel<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<float>(x), mp<float>(r),
+                           cp<float>(p), cp<float>(Ap), sc, n);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_pcg_p(void* p, const void* z, const double* sc, int dtype, int64_t n, hipStream_t s) {
+    if (dtype == PA_F64)
+        hipLaunchKernelGGL(pcg_p_kernel<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<double>(p), cp<double>(z),
+                           sc, n);
+    else
+        hipLaunchKernelGGL(pcg_p_kernel<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<float>(p), cp<float>(z), sc,
+                           n);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_axpby(void* y, const void* x, double a, double b, int dtype, int64_t n, hipStream_t s) {
+    if (dtype == PA_F64)
+        hipLaunchKernelGGL(axpby_kernel<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<double>(y), cp<double>(x),
+                           a, b, n);
+    else
+        hipLaunchKernelGGL(axpby_kernel<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<float>(y), cp<float>(x), a,
+                           b, n);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_residual(void* r, const void* b, const void* Ax, int dtype, int64_t n, hipStream_t s) {
+    if (dtype == PA_F64)
+        hipLaunchKernelGGL(residual_kernel<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<double>(r),
+                           cp<double>(b), cp<double>(Ax), n);
+    else
+        hipLaunchKernelGGL(residual_kernel<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<float>(r), cp<float>(b),
+                           cp<float>(Ax), n);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_copy(void* y, const void* x, int dtype, int64_t n, hipStream_t s) {
+    if (dtype == PA_F64)
+        hipLaunchKernelGGL(copy_kernel<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<double>(y), cp<double>(x), n);
+    else
+        hipLaunchKernelGGL(copy_kernel<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<float>(y), cp<float>(x), n);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_cast_scale(void* y, int dty, const void* x, int dtx, const double* sc, int slot, int inv_sqrt, int64_t n,
+                      hipStream_t s) {
+    const dim3 g(grid_for(n)), b(kBlock);
+    if (dty == PA_F32 && dtx == PA_F64)
+        hipLaunchKernelGGL((cast_scale_kernel<float, double>), g, b, 0, s, mp<float>(y), cp<double>(x), sc, slot, inv_sqrt, n);
+    else if (dty == PA_F64 && dtx == PA_F64)
+        hipLaunchKernelGGL((cast_scale_kernel<double, double>), g, b, 0, s, mp<double>(y), cp<double>(x), sc, slot, inv_sqrt, n);
+    else if (dty == PA_F64 && dtx == PA_F32)
+        hipLaunchKernelGGL((cast_scale_kernel<double, float>), g, b, 0, s, mp<double>(y), cp<float>(x), sc, slot, inv_sqrt, n);
+    else
+        hipLaunchKernelGGL((cast_scale_kernel<float, float>), g, b, 0, s, mp<float>(y), cp<float>(x), sc, slot, inv_sqrt, n);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_ir_update(double* x, const void* d, int dtd, const double* sc, int slot, int64_t n, hipStream_t s) {
+    if (dtd == PA_F64)
+        hipLaunchKernelGGL(ir_update_kernel<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, x, cp<double>(d), sc, slot, n);
+    else
+        hipLaunchKernelGGL(ir_update_kernel<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, x, cp<float>(d), sc, slot, n);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_cheb_step(void* x, void* r, const void* t, void* d, const void* dinv, double c1, double c2, int dtype,
+                     int64_t n, hipStream_t s) {
+    if (dtype == PA_F64)
+        hipLaunchKernelGGL(cheb_step_kernel<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<double>(x),
+                           mp<double>(r), cp<double>(t), mp<double>(d), cp<double>(dinv), c1, c2, n);
+    else
+        hipLaunchKernelGGL(cheb_step_kernel<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<float>(x), mp<float>(r),
+                           cp<float>(t), mp<float>(d), cp<float>(dinv), c1, c2, n);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_cheb_first(void* d, const void* dinv, const void* r, double c, int dtype, int64_t n, hipStream_t s) {
+    if (dtype == PA_F64)
+        hipLaunchKernelGGL(cheb_first_kernel<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<double>(d),
+                           cp<double>(dinv), cp<double>(r), c, n);
+    else
+        hipLaunchKernelGGL(cheb_first_kernel<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<float>(d),
+                           cp<float>(dinv), cp<float>(r), c, n);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_add(void* y, const void* x, int dtype, int64_t n, hipStream_t s) {
+    if (dtype == PA_F64)
+        hipLaunchKernelGGL(add_kernel<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<double>(y), cp<double>(x), n);
+    else
+        hipLaunchKernelGGL(add_kernel<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<float>(y), cp<float>(x), n);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_reciprocal(void* y, int dtype, int64_t n, hipStream_t s) {
+    if (dtype == PA_F64)
+        hipLaunchKernelGGL(reciprocal_kernel<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<double>(y), n);
+    else
+        hipLaunchKernelGGL(reciprocal_kernel<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<float>(y), n);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_splitmix(void* v, int dtype, uint64_t seed, int64_t n, hipStream_t s) {
+    if (dtype == PA_F64)
+        hipLaunchKernelGGL(splitmix_kernel<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<double>(v), seed, n);
+    else
+        hipLaunchKernelGGL(splitmix_kernel<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<float>(v), seed, n);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_p_interp_matrix(const double* gll_c, const double* gll_f, int pc, int pf, double* I, hipStream_t s) {
+    hipLaunchKernelGGL(p_interp_matrix_kernel, dim3(1), dim3(128), 0, s, gll_c, gll_f, pc, pf, I);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+static size_t p_transfer_lds(int pc, int pf) {
+    const int Dc = pc + 1, Df = pf + 1;
+    const size_t a = 3 * Dc * Dc * Dc + 3 * Dc * Dc * Df + 3 * Dc * Df * Df + Df * Dc;
+    const size_t b = 3 * Df * Df * Df + 3 * Df * Df * Dc + 3 * Df * Dc * Dc + Df * Dc;
+    return (a > b ? a : b) * sizeof(double);
+}
+
+int launch_p_prolong(const void* xc, void* xf, const double* I, int pc, int pf, const Geom& gc, const Geom& gf,
+                     int add, int dtype, hipStream_t s) {
+    const size_t lds = p_transfer_lds(pc, pf);
+    if (dtype == PA_F64)
+        hipLaunchKernelGGL(p_prolong_kernel<double>, dim3(gf.NE), dim3(128), lds, s, cp<double>(xc), mp<double>(xf),
+                           I, pc, pf, gc, gf, add);
+    else
+        hipLaunchKernelGGL(p_prolong_kernel<float>, dim3(gf.NE), dim3(128), lds, s, cp<float>(xc), mp<float>(xf), I,
+                           pc, pf, gc, gf, add);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_p_restrict(const void* rf, void* rc, const double* I, int pc, int pf, const Geom& gc, const Geom& gf,
+                      int dtype, hipStream_t s) {
+    int rcode = launch_fill(rc, dtype, 3 * (int64_t)gc.Nn, 0.0, s);
+    if (rcode) return rcode;
+    const size_t lds = p_transfer_lds(pc, pf);
+    if (dtype == PA_F64)
+        hipLaunchKernelGGL(p_restrict_kernel<double>, dim3(gf.NE), dim3(128), lds, s, cp<double>(rf), mp<double>(rc),
+                           I, pc, pf, gc, gf);
+    else
+        hipLaunchKernelGGL(p_restrict_kernel<float>, dim3(gf.NE), dim3(128), lds, s, cp<float>(rf), mp<float>(rc), I,
+                           pc, pf, gc, gf);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_h_prolong(const void* xc, void* xf, const HAxis ax[3], const Geom& gc, const Geom& gf, int add, int dtype,
+                     hipStream_t s) {
+    const int g = grid_for(gf.Nn);
+    if (dtype == PA_F64)
+        hipLaunchKernelGGL(h_prolong_kernel<double>, dim3(g), dim3(kBlock), 0, s, cp<double>(xc), mp<double>(xf), ax[0],
+                           ax[1], ax[2], gc, gf, add);
+    else
+        hipLaunchKernelGGL(h_prolong_kernel<float>, dim3(g), dim3(kBlock), 0, s, cp<float>(xc), mp<float>(xf), ax[0],
+                           ax[1], ax[2], gc, gf, add);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_h_restrict(const void* rf, void* rc, const HAxis ax[3], const Geom& gc, const Geom& gf, int dtype,
+                      hipStream_t s) {
+    const int g = grid_for(gc.Nn);
+    if (dtype == PA_F64)
+        hipLaunchKernelGGL(h_restrict_kernel<double>, dim3(g), dim3(kBlock), 0, s, cp<double>(rf), mp<double>(rc),
+                           ax[0], ax[1], ax[2], gc, gf);
+    else
+        hipLaunchKernelGGL(h_restrict_kernel<float>, dim3(g), dim3(kBlock), 0, s, cp<float>(rf), mp<float>(rc), ax[0],
+                           ax[1], ax[2], gc, gf);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_coarse_assemble(double* A, int N, const pa_op* op, hipStream_t s) {
+    const Geom g = make_geom(op->mesh, op->p, true);
+    int rc = launch_fill(A, PA_F64, (int64_t)N * N, 0.0, s);
+    if (rc) return rc;
+    const int D3 = (op->p + 1) * (op->p + 1) * (op->p + 1);
+    const long long work = (long long)g.NE * D3 * D3;
+    const int nb = (int)((work + 255) / 256);
+    if (op->dtype == PA_F64)
+        hipLaunchKernelGGL(coarse_assemble_kernel<double>, dim3(nb), dim3(256), 0, s, A, N, cp<double>(op->ed),
+                           op->d_tab, op->p, op->q, g);
+    else
+        hipLaunchKernelGGL(coarse_assemble_kernel<float>, dim3(nb), dim3(256), 0, s, A, N, cp<float>(op->ed),
+                           op->d_tab, op->p, op->q, g);
+    PA_CHECK_LAUNCH();
+    hipLaunchKernelGGL(coarse_constrain_kernel, dim3(grid_for((int64_t)N * N)), dim3(kBlock), 0, s, A, N, g);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int coarse_invert(double* A, double* col, int N, hipStream_t s) {
+    const int g1 = grid_for(N), g2 = grid_for((int64_t)N * N);
+    for (int k = 0; k < N; ++k) {
+        hipLaunchKernelGGL(gj_save_col_kernel, dim3(g1), dim3(kBlock), 0, s, A, col, N, k);
+        hipLaunchKernelGGL(gj_update_kernel, dim3(g2), dim3(kBlock), 0, s, A, col, N, k);
+        hipLaunchKernelGGL(gj_pivot_row_kernel, dim3(g1), dim3(kBlock), 0, s, A, col, N, k);
+    }
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_dense_cast(void* out, int dtype, const double* in, int64_t n, hipStream_t s) {
+    if (dtype == PA_F64)
+        hipLaunchKernelGGL(dense_cast_kernel<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<double>(out), in, n);
+    else
+        hipLaunchKernelGGL(dense_cast_kernel<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<float>(out), in, n);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_dense_matvec(const void* Ai, const void* x, void* y, int N, int dtype, hipStream_t s) {
+    const int rows_per_block = 4;
+    const int nb = (N + rows_per_block - 1) / rows_per_block;
+    if (dtype == PA_F64)
+        hipLaunchKernelGGL(dense_matvec_kernel<double>, dim3(nb), dim3(64 * rows_per_block), 0, s, cp<double>(Ai),
+                           cp<double>(x), mp<double>(y), N);
+    else
+        hipLaunchKernelGGL(dense_matvec_kernel<float>, dim3(nb), dim3(64 * rows_per_block), 0, s, cp<float>(Ai),
+                           cp<float>(x), mp<float>(y), N);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+}  // namespace pa
