@@ -583,10 +583,12 @@ int outer_residual(pa_solve* S, double* r, double* tmp) {
 
 int enqueue_inner_batch(pa_solve* S, int n) {
     const pa_solve_opts_t& o = S->G->opts;
-    const int cap = S->G->vdtype == PA_F32 ? o.inner_max_iter : o.max_iter;
+    const bool ir = S->G->vdtype == PA_F32;
     int rc;
-    for (int i = 0; i < n && S->inner_iters < cap; ++i)
+    for (int i = 0; i < n; ++i) {
+        if (ir ? S->inner_iters >= o.inner_max_iter : S->total_iters >= o.max_iter) break;
         if ((rc = inner_iteration(S))) return rc;
+    }
     return enqueue_copy_event(S);
 }
 
@@ -623,10 +625,28 @@ int solve_advance(pa_solve* S, int batch, bool may_enqueue) {
     int rc;
     if (S->phase == 2) return PA_OK;
     if (G->vdtype == PA_F64) {
+        if (S->phase == 1) {
+            // true-residual check after the recursive residual met the test: the recursion
+            // drifts from b - A x, so restart from the current x when the true one is too big
+            const double nr = std::sqrt(h[S_NR]), nb = std::sqrt(h[S_NB]);
+            if ((nb > 0.0 ? nr / nb : 0.0) <= S->rtol || nr == 0.0) { S->phase = 2; S->status = PA_OK; return PA_OK; }
+            if (S->total_iters >= o.max_iter || S->outer >= 8) { S->phase = 2; S->status = PA_ENOCONV; return PA_OK; }
+            if (!may_enqueue) return PA_OK;
+            S->outer++;
+            if ((rc = inner_begin(S, S->rtol, o.stop))) return rc;   // pr already holds b - A x
+            S->phase = 0;
+            return enqueue_inner_batch(S, batch);
+        }
         S->crit_prec = h[S_CRIT];
-        if (h[S_DONE] == 1.0) { S->phase = 2; S->status = PA_OK; return PA_OK; }
         if (h[S_DONE] == 2.0) { S->phase = 2; S->status = PA_EBREAKDOWN; return PA_OK; }
-        if (S->inner_iters >= o.max_iter) { S->phase = 2; S->status = PA_ENOCONV; return PA_OK; }
+        if (h[S_DONE] == 1.0) {
+            if (o.stop != PA_STOP_TRUE) { S->phase = 2; S->status = PA_OK; return PA_OK; }
+            if (!may_enqueue) return PA_OK;
+            if ((rc = outer_residual(S, (double*)G->pr, (double*)G->pAp))) return rc;
+            S->phase = 1;
+            return enqueue_copy_event(S);
+        }
+        if (S->total_iters >= o.max_iter) { S->phase = 2; S->status = PA_ENOCONV; return PA_OK; }
         if (!may_enqueue) return PA_OK;
         return enqueue_inner_batch(S, batch);
     }
@@ -635,14 +655,12 @@ int solve_advance(pa_solve* S, int batch, bool may_enqueue) {
         const double nr = std::sqrt(h[S_NR]), nb = std::sqrt(h[S_NB]);
         const double crit = nb > 0.0 ? nr / nb : 0.0;
         if (crit <= S->rtol || nr == 0.0) { S->phase = 2; S->status = PA_OK; return PA_OK; }
-        if (S->outer > 0 && crit >= 0.5 * S->last_outer) {
-            if (++S->stall >= 3) { S->phase = 2; S->status = PA_ENOCONV; return PA_OK; }
-        } else {
-            S->stall = 0;
-        }
         if (S->outer >= o.max_outer) { S->phase = 2; S->status = PA_ENOCONV; return PA_OK; }
-        S->last_outer = crit;
+        const bool stalled = S->outer > 0 && crit >= 0.5 * S->last_outer;
+        if (stalled && S->stall + 1 >= 3) { S->phase = 2; S->status = PA_ENOCONV; return PA_OK; }
         if (!may_enqueue) return PA_OK;
+        S->stall = stalled ? S->stall + 1 : 0;
+        S->last_outer = crit;
         // inner solve of A d = r / |r| in FP32 from d = 0
         if ((rc = launch_cast_scale(G->pr, PA_F32, G->r64, PA_F64, G->scal, S_NR, 1, G->fine64->N, G->stream)))
             return rc;
