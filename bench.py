@@ -104,6 +104,11 @@ def main(argv=None):
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--solve", action="store_true", help="also time the cantilever GMG-PCG solves")
     ap.add_argument("--serve", type=int, default=0, help="also run a serving stream of this many requests")
+    ap.add_argument("--profile-apply", type=int, default=0, metavar="P",
+                    help="profiling mode: only run --reps applies of the degree-P sheared-box operator "
+                         "(then three 256 MiB copies that calibrate the traffic counters) and exit")
+    ap.add_argument("--dtype", choices=("f64", "f32"), default="f64")
+    ap.add_argument("--reps", type=int, default=10)
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -135,6 +140,20 @@ def main(argv=None):
         xs = [x0.clone() for _ in range(K)]
         ys = [torch.empty_like(x0) for _ in range(K)]
         return dict(op=op, xs=xs, ys=ys, N=op.N, NE=mesh.num_elements, word=word, p=p, dtype=dtype)
+
+    if args.profile_apply:
+        s = make(args.profile_apply, pa.PA_F64 if args.dtype == "f64" else pa.PA_F32)
+        K = len(s["xs"])
+        for i in range(args.reps):
+            s["op"].apply(s["xs"][i % K], s["ys"][i % K])
+        a = torch.empty(32 << 20, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_apply": args.profile_apply, "dtype": args.dtype, "reps": args.reps,
+                          "N": s["N"], "NE": s["NE"], "calibration_copy_bytes": a.numel() * 8}), flush=True)
+        return 0
 
     # ---------------- timed step: FP64 apply at every p of the sweep
     setups = {p: make(p, pa.PA_F64) for p in STEP_PS}
@@ -178,7 +197,7 @@ def main(argv=None):
     tr = MEASURED_TRAFFIC.get((src_hash, pdom, "f64"))
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_F64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_F64_TFLOPS, 4), "traffic": tr,
-                "kernel": f"pa_apply_kernel<P={pdom},Q={pdom + 2},double> (+ y-init)",
+                "kernel": f"pa_apply_kernel<P={pdom},Q={pdom + 2},double> + pa_skeleton_kernel<P={pdom},double>",
                 "flops_per_launch": flops,
                 "algorithmic_bytes_per_launch": algorithmic_bytes(sd["N"], sd["NE"], 8),
                 "hbm_gbs": round(algorithmic_bytes(sd["N"], sd["NE"], 8) / t_launch / 1e9, 1),

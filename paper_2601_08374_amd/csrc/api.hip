@@ -93,6 +93,7 @@ int create_op(const MeshDesc& md, int p, int q, const double* lam, const double*
         if (rc) break;
         if (hipMalloc(&op->d_vert, nvert * sizeof(double)) != hipSuccess ||
             hipMalloc(&op->ed, (size_t)NE * kEdStride * esz) != hipSuccess ||
+            hipMalloc(&op->sk, (size_t)skeleton_words(p, NE) * esz) != hipSuccess ||
             hipMalloc(&d_lm, 2 * (size_t)NE * sizeof(double)) != hipSuccess) {
             (void)hipGetLastError();
             rc = fail(PA_ENOMEM, "device allocation failed (%lld elements)", (long long)NE);
@@ -126,12 +127,11 @@ int apply_op(const pa_op* op, const void* x, void* y, int flags) {
     L.g = make_geom(op->mesh, op->p, constrained);
     L.x = x;
     L.y = y;
+    L.sk = op->sk;
     L.ed = op->ed;
     L.tab = &op->tab;
     L.add = add;
     L.stream = op->stream;
-    int rc = launch_apply_prep(x, y, op->dtype, L.g, add, op->stream);
-    if (rc) return rc;
     const int qo = op->q - op->p - 1;
     switch (op->p) {
         case 1: return launch_apply_p1(L, qo, op->dtype);
@@ -189,6 +189,7 @@ void pa_elast_destroy(pa_op_t* op) {
     if (!op) return;
     if (op->cached) gmg_destroy(op->cached);
     if (op->ed) (void)hipFree(op->ed);
+    if (op->sk) (void)hipFree(op->sk);
     if (op->d_tab) (void)hipFree(op->d_tab);
     if (op->d_vert) (void)hipFree(op->d_vert);
     delete op;

@@ -1,22 +1,32 @@
 // Fused matrix-free apply of the linear-elasticity operator on affine hexahedra.
 //
-// One kernel performs, per element (paper Sec. 4.2 macro-kernel fusion, Sec. 4.4
-// sum factorization, Sec. 4.5 Voigt stress and backward sweeps):
-//   gather x_e (restriction G)                    -> LDS tile [3][D^3]
-//   forward X:  u = sum_ix x B, v = sum_ix x G    -> LDS [2][D][D][Q]
-//   forward Y:  (v B, u G, u B) over iy            -> LDS [3][D][Q][Q]
-//   forward Z:  over iz into a register column per (qx,qy): 3 comps x 3 dirs x Q
-//   pointwise:  grad = J^{-T} ref-grad; Voigt sigma with w*detJ*lambda, w*detJ*mu;
-//               Q_{c,m} = sum_i sigma_{c,i} J^{-1}_{m,i}   (in place in registers)
-//   backward Z (registers -> LDS), Y, X (m-channels summed where B/G coincide),
-//   scatter-add into y (G^T) with hardware FP atomics.
+// Kernel 1 (pa_apply_kernel), per element and per displacement component c
+// (paper Sec. 4.2 macro-kernel fusion, Sec. 4.4 sum factorization, Sec. 4.5
+// Voigt stress and transposed sweeps):
+//   gather x_c (restriction G, clamped entries read as 0)   -> LDS [D][D][D]
+//   forward X:  u = x B, v = x G        (lines (iz,iy))      -> LDS [2][D][D][Q]
+//   forward Y:  (v B, u G, u B)         (lines (iz,qx))      -> LDS [3][D][Q][Q]
+//   forward Z:  into a register column per (qx,qy): ref-gradient [c][m][qz]
+// then pointwise, in registers: grad = J^{-T} ref-grad, Voigt stress with the
+// weighted w*detJ*lambda, w*detJ*mu (eq. 7), Q_{c,m} = sum_i sigma_{c,i} J^{-1}_{m,i};
+// then per output component: backward Z (column -> LDS), Y, X (the m-channels
+// that share a 1D factor are summed before the next sweep), and the scatter:
+// nodes strictly inside the element are written to y by their only owner;
+// element-boundary ("skeleton") contributions go to a per-element buffer.
+// Kernel 2 (pa_skeleton_kernel) sums, for every element-boundary node, the
+// contributions of its (up to 8) elements in a fixed order and writes y -- no
+// atomics, no separate initialisation of y, bitwise-reproducible results.
 //
-// Design for gfx950: the 1D tables B, G, w are kernel arguments (kernarg segment),
-// so every contraction reads them with scalar loads as wave-uniform SGPR operands
-// of the FMAs; lanes map to distinct 1D lines, each lane contracting a whole line
-// with its inputs in VGPRs (no per-FMA LDS traffic).  LDS only transposes data
-// between the X, Y and Z passes.  Several elements share a workgroup at low p so
-// that the (qx,qy) columns fill 64-wide wavefronts.
+// Every 1D contraction uses the even-odd decomposition: on the symmetric
+// Gauss-Lobatto / Gauss-Legendre point sets B[i][k] = B[D-1-i][Q-1-k] and
+// G[i][k] = -G[D-1-i][Q-1-k], so pairs of outputs k, Q-1-k come from the sums
+// and differences of mirrored inputs with half-size tables (half the FMAs).
+//
+// gfx950 mapping: the even-odd tables are kernel arguments (kernarg segment), so
+// contractions read them with scalar loads as wave-uniform SGPR operands; lanes
+// map to whole 1D lines (inputs in VGPRs, no per-FMA LDS traffic); LDS only
+// transposes between sweeps, with odd row strides against bank conflicts.
+// Several elements share a workgroup at low p to fill 64-wide wavefronts.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,23 +36,164 @@
 
 namespace pa {
 
+// ---------------------------------------------------------------- even-odd tables
+// For M (NI x NO) with M[i][k] = SIGN * M[NI-1-i][NO-1-k]:
+//   P[i][k] = (M[i][k] + M[NI-1-i][k]) / 2 (i < NI/2),  P[NI/2][k] = M[NI/2][k] for odd NI;
+//   N[i][k] = (M[i][k] - M[NI-1-i][k]) / 2 (i < NI/2);   k < ceil(NO/2).
+template <typename T, int NI, int NO>
+struct EOTab {
+    static constexpr int hI = NI / 2, mI = NI & 1, hO = NO / 2, mO = NO & 1, KO = hO + mO;
+    T P[(hI + mI) * KO];
+    T N[(hI > 0 ? hI : 1) * KO];
+};
+
+template <typename T, int NI, int NO>
+inline void fill_eo(EOTab<T, NI, NO>& t, const double* M /* M[i*NO+k] */) {
+    using E = EOTab<T, NI, NO>;
+    for (int k = 0; k < E::KO; ++k) {
+        for (int i = 0; i < E::hI; ++i) {
+            t.P[i * E::KO + k] = (T)(0.5 * (M[i * NO + k] + M[(NI - 1 - i) * NO + k]));
+            t.N[i * E::KO + k] = (T)(0.5 * (M[i * NO + k] - M[(NI - 1 - i) * NO + k]));
+        }
+        if (E::mI) t.P[E::hI * E::KO + k] = (T)M[E::hI * NO + k];
+    }
+}
+
+// out[k] = sum_i in[i] M[i][k] for every k (ADD: out += ...), even-odd form.
+template <int SIGN, bool ADD, typename T, int NI, int NO>
+__device__ __forceinline__ void eo_contract(const T (&in)[NI], T (&out)[NO], const EOTab<T, NI, NO>& t) {
+    using E = EOTab<T, NI, NO>;
+    constexpr int hI = E::hI, mI = E::mI, hO = E::hO, mO = E::mO, KO = E::KO;
+    T s[hI > 0 ? hI : 1], a[hI > 0 ? hI : 1];
+#pragma unroll
+    for (int i = 0; i < hI; ++i) {
+        s[i] = in[i] + in[NI - 1 - i];
+        a[i] = in[i] - in[NI - 1 - i];
+    }
+#pragma unroll
+    for (int k = 0; k < KO; ++k) {
+        T sp = T(0), an = T(0);   // symmetric-input part (P) and antisymmetric-input part (N)
+        const bool mid = (mO && k == hO);
+        if (SIGN > 0 || !mid) {
+#pragma unroll
+            for (int i = 0; i < hI; ++i) sp = fma(s[i], t.P[i * KO + k], sp);
+            if (mI) sp = fma(in[hI], t.P[hI * KO + k], sp);
+        }
+        if (SIGN < 0 || !mid) {
+#pragma unroll
+            for (int i = 0; i < hI; ++i) an = fma(a[i], t.N[i * KO + k], an);
+        }
+        // SIGN > 0: out[k] = sp + an, out[NO-1-k] = sp - an ; SIGN < 0: out[k] = an + sp, out[NO-1-k] = an - sp
+        const T ev = SIGN > 0 ? sp : an, od = SIGN > 0 ? an : sp;
+        if (mid) {
+            if (ADD) out[k] += ev; else out[k] = ev;
+        } else {
+            if (ADD) { out[k] += ev + od; out[NO - 1 - k] += ev - od; }
+            else { out[k] = ev + od; out[NO - 1 - k] = ev - od; }
+        }
+    }
+}
+
+// Plain table M[i][k] (NI x NO) for the low orders, where the even-odd form would
+// spend more additions than it saves multiplications.
+template <typename T, int NI, int NO>
+struct DTab {
+    T M[NI * NO];
+};
+
+template <typename T, int NI, int NO>
+inline void fill_direct(DTab<T, NI, NO>& t, const double* M) {
+    for (int i = 0; i < NI * NO; ++i) t.M[i] = (T)M[i];
+}
+
+template <int SIGN, bool ADD, typename T, int NI, int NO>
+__device__ __forceinline__ void eo_contract(const T (&in)[NI], T (&out)[NO], const DTab<T, NI, NO>& t) {
+#pragma unroll
+    for (int k = 0; k < NO; ++k) {
+        T acc = ADD ? out[k] : T(0);
+#pragma unroll
+        for (int i = 0; i < NI; ++i) acc = fma(in[i], t.M[i * NO + k], acc);
+        out[k] = acc;
+    }
+}
+
+// Two operators applied to two inputs and summed: out = in1 M1 + in2 M2.
+template <int S1, int S2, typename T, int NI, int NO, class TAB>
+__device__ __forceinline__ void eo_contract2(const T (&in1)[NI], const TAB& t1, const T (&in2)[NI], const TAB& t2,
+                                             T (&out)[NO]) {
+    eo_contract<S1, false>(in1, out, t1);
+    eo_contract<S2, true>(in2, out, t2);
+}
+
+// Even-odd tables from p = 4 on (D >= 5); plain tables below.
+template <typename T, int NI, int NO, bool EO = (NI >= 5 && NO >= 5)>
+struct TabSel {
+    using type = EOTab<T, NI, NO>;
+    static void fill(type& t, const double* M) { fill_eo<T, NI, NO>(t, M); }
+};
+template <typename T, int NI, int NO>
+struct TabSel<T, NI, NO, false> {
+    using type = DTab<T, NI, NO>;
+    static void fill(type& t, const double* M) { fill_direct<T, NI, NO>(t, M); }
+};
+
 template <typename T, int D, int Q>
-struct Tab1D {
-    T B[D * Q];
-    T G[D * Q];
+struct ApplyTabs {
+    typename TabSel<T, D, Q>::type Bf, Gf;   // forward: nodal (D) -> quadrature (Q)
+    typename TabSel<T, Q, D>::type Bt, Gt;   // backward: quadrature (Q) -> nodal (D)
     T w[Q];
 };
 
 template <typename T, int D, int Q>
-inline Tab1D<T, D, Q> make_tab(const Tables& t) {
-    Tab1D<T, D, Q> r;
-    for (int i = 0; i < D * Q; ++i) { r.B[i] = (T)t.B[i]; r.G[i] = (T)t.G[i]; }
+inline ApplyTabs<T, D, Q> make_tabs(const Tables& t) {
+    ApplyTabs<T, D, Q> r;
+    double Bt[D * Q], Gt[D * Q];
+    for (int i = 0; i < D; ++i)
+        for (int k = 0; k < Q; ++k) {
+            Bt[k * D + i] = t.B[i * Q + k];
+            Gt[k * D + i] = t.G[i * Q + k];
+        }
+    TabSel<T, D, Q>::fill(r.Bf, t.B);
+    TabSel<T, D, Q>::fill(r.Gf, t.G);
+    TabSel<T, Q, D>::fill(r.Bt, Bt);
+    TabSel<T, Q, D>::fill(r.Gt, Gt);
     for (int k = 0; k < Q; ++k) r.w[k] = (T)t.w[k];
     return r;
 }
 
-__device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
-__device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
+// ---------------------------------------------------------------- skeleton numbering
+// Element-boundary ("skeleton") local nodes (some index 0 or p), numbered in
+// lexicographic (iz, iy, ix) order: full layers iz = 0 and iz = p hold D*D nodes,
+// inner layers 4(D-1) nodes (rows iy = 0 and iy = p complete, inner rows ix = 0, p).
+template <int D>
+struct Skel {
+    static constexpr int P = D - 1;
+    static constexpr int S = D * D * D - (D - 2) * (D - 2) * (D - 2);
+    static constexpr int LAYER = 4 * (D - 1);
+    __device__ __forceinline__ static int index(int ix, int iy, int iz) {
+        int base, off;
+        if (iz == 0 || iz == P) {
+            base = (iz == 0) ? 0 : D * D + (D - 2) * LAYER;
+            off = iy * D + ix;
+        } else {
+            base = D * D + (iz - 1) * LAYER;
+            if (iy == 0) off = ix;
+            else if (iy == P) off = D + 2 * (D - 2) + ix;
+            else off = D + 2 * (iy - 1) + (ix == P ? 1 : 0);
+        }
+        return base + off;
+    }
+    __device__ __forceinline__ static bool interior(int ix, int iy, int iz) {
+        return ix > 0 && ix < P && iy > 0 && iy < P && iz > 0 && iz < P;
+    }
+    // Buffer layout: element-major ([e][c][s]) from p = 3 on, so that consecutive nodes
+    // of one element face are contiguous; node-major ([c][s][e]) at p <= 2, where
+    // consecutive nodes belong to consecutive elements.
+    static constexpr bool ELEM_MAJOR = D >= 4;
+    __device__ __forceinline__ static size_t offset(int e, int c, int s, int NE) {
+        return ELEM_MAJOR ? ((size_t)e * 3 + c) * S + s : ((size_t)c * S + s) * NE + e;
+    }
+};
 
 // Elements per workgroup: fill 64-lane waves with the E*Q*Q quadrature columns while
 // keeping the workgroup's LDS at or below 64 KiB.
@@ -50,7 +201,13 @@ template <int P, int Q, typename T>
 struct ApplyCfg {
     static constexpr int D = P + 1;
     static constexpr int QQ = Q * Q;
-    static constexpr int LDS_ELEM = 3 * D * D * D + 2 * D * D * Q + 3 * D * Q * Q;  // words / element
+    static constexpr int DP = D | 1;   // padded row strides (odd, in words)
+    static constexpr int QP = Q | 1;
+    static constexpr int XT = D * D * DP;                  // gather / output tile of one component
+    static constexpr int UT = 2 * D * D * QP;              // X-pass output (two channels)
+    static constexpr int ST = 3 * D * QQ;                  // Y-pass output (three channels)
+    static constexpr int RA = ST > XT ? ST : XT;           // region shared by the tile and the Y output
+    static constexpr int LDS_ELEM = RA + UT;
     static constexpr int pickE() {
         int bestE = 1;
         double bestU = 0.0;
@@ -77,118 +234,120 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 
 template <int P, int Q, typename T>
 __global__ void __launch_bounds__((ApplyCfg<P, Q, T>::NT))
-pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ ed,
-                const Tab1D<T, P + 1, Q> tab, const Geom g) {
+pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, const T* __restrict__ ed,
+                const ApplyTabs<T, P + 1, Q> tab, const Geom g, const int add) {
     using C = ApplyCfg<P, Q, T>;
+    using SK = Skel<P + 1>;
     constexpr int D = P + 1, E = C::E, NT = C::NT, QQ = Q * Q;
-    constexpr int D3 = D * D * D;
-    constexpr int XS = 3 * D3;          // gather/scatter tile per element
-    constexpr int US = 2 * D * D * Q;   // X-pass output per element
-    constexpr int SS = 3 * D * Q * Q;   // Y-pass output per element
-    __shared__ T Xs[E * XS];
-    __shared__ T Us[E * US];
-    __shared__ T Ss[E * SS];
+    constexpr int DP = C::DP, QP = C::QP;
+    constexpr int XT = C::XT, UT = C::UT, RA = C::RA;
+    constexpr int S = SK::S;
+    __shared__ T Ra[E * RA];     // gather tile | Y-pass output | backward Z output | output tile
+    __shared__ T Ua[E * UT];     // X-pass output | backward Y output
+    __shared__ int ebase[E];     // first node of each element, or -1 past the end
+    __shared__ int ecoord[E][3];
 
     const int tid = threadIdx.x;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int e0 = blk * E;
-
-    // ---- gather (restriction G): x -> Xs[el][c][iz][iy][ix]
-    for (int w = tid; w < E * XS; w += NT) {
-        const int el = w / XS, r = w % XS;
-        const int c = r / D3, a = r % D3;
-        const int ix = a % D, iy = (a / D) % D, iz = a / (D * D);
-        const int e = e0 + el;
-        T v = T(0);
+    if (tid < E) {
+        const int e = e0 + tid;
         if (e < g.NE) {
-            const int ex = e % g.nx, ey = (e / g.nx) % g.ny, ez = e / (g.nx * g.ny);
-            const int gx = ex * P + ix, gy = ey * P + iy, gz = ez * P + iz;
-            if (!clamped_node(g.clamp, gx, gy, gz, g))
-                v = x[(size_t)c * g.Nn + gx + g.Nx * (gy + g.Ny * gz)];
+            const int ex = e % g.nx, r = e / g.nx;
+            const int ey = r % g.ny, ez = r / g.ny;
+            ecoord[tid][0] = ex * P;
+            ecoord[tid][1] = ey * P;
+            ecoord[tid][2] = ez * P;
+            ebase[tid] = ex * P + g.Nx * (ey * P + g.Ny * ez * P);
+        } else {
+            ebase[tid] = -1;
         }
-        Xs[w] = v;
     }
 
-    // column owned by this thread in the Z / pointwise stage
     const int cel = tid / QQ, cq = tid % QQ;
     const int cqx = cq % Q, cqy = cq / Q;
     const bool has_col = tid < E * QQ;
     T gq[3][3][Q];   // [component][reference direction][qz]
-
-    __syncthreads();
+    const size_t NN = (size_t)g.Nn;
 
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
+        __syncthreads();   // ebase ready (c = 0) / previous Z pass done reading Ra
+        // ---- gather component c: Ra[el][iz][iy][ix] (row stride DP); at low p consecutive
+        // lanes take consecutive elements (contiguous in x), else consecutive local nodes
+        for (int w = tid; w < E * D * D * D; w += NT) {
+            const int el = SK::ELEM_MAJOR ? w / (D * D * D) : w % E;
+            const int a = SK::ELEM_MAJOR ? w % (D * D * D) : w / E;
+            const int ix = a % D, iy = (a / D) % D, iz = a / (D * D);
+            const int b = ebase[el];
+            T v = T(0);
+            if (b >= 0) {
+                bool cl = false;
+                if (g.clamp)
+                    cl = clamped_node(g.clamp, ecoord[el][0] + ix, ecoord[el][1] + iy, ecoord[el][2] + iz, g);
+                if (!cl) v = x[c * NN + b + ix + g.Nx * (iy + g.Ny * iz)];
+            }
+            Ra[el * RA + (iz * D + iy) * DP + ix] = v;
+        }
+        __syncthreads();
         // ---- forward X: lines (el, iz, iy)
         for (int w = tid; w < E * D * D; w += NT) {
             const int el = w / (D * D), r = w % (D * D);
-            const T* xin = Xs + el * XS + c * D3 + r * D;
-            T xv[D];
+            const T* xin = Ra + el * RA + r * DP;
+            T xv[D], u[Q], v[Q];
 #pragma unroll
             for (int i = 0; i < D; ++i) xv[i] = xin[i];
-            T* uo = Us + el * US + r * Q;
+            eo_contract<1, false>(xv, u, tab.Bf);
+            eo_contract<-1, false>(xv, v, tab.Gf);
+            T* uo = Ua + el * UT + r * QP;
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
-                T u = T(0), v = T(0);
-#pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    u = fma(xv[i], tab.B[i * Q + k], u);
-                    v = fma(xv[i], tab.G[i * Q + k], v);
-                }
-                uo[k] = u;
-                uo[D * D * Q + k] = v;
+                uo[k] = u[k];
+                uo[D * D * QP + k] = v[k];
             }
         }
         __syncthreads();
-        // ---- forward Y: lines (el, iz, qx)
+        // ---- forward Y: lines (el, iz, qx): s0 = v B (d/dxi), s1 = u G (d/deta), s2 = u B
         for (int w = tid; w < E * D * Q; w += NT) {
             const int el = w / (D * Q), r = w % (D * Q);
             const int iz = r / Q, qx = r % Q;
-            const T* ui = Us + el * US + iz * D * Q + qx;
-            T uv[D], vv[D];
+            const T* ui = Ua + el * UT + iz * D * QP + qx;
+            T uv[D], vv[D], s0[Q], s1[Q], s2[Q];
 #pragma unroll
-            for (int i = 0; i < D; ++i) { uv[i] = ui[i * Q]; vv[i] = ui[D * D * Q + i * Q]; }
-            T* so = Ss + el * SS + iz * QQ + qx;
+            for (int i = 0; i < D; ++i) { uv[i] = ui[i * QP]; vv[i] = ui[D * D * QP + i * QP]; }
+            eo_contract<1, false>(vv, s0, tab.Bf);
+            eo_contract<-1, false>(uv, s1, tab.Gf);
+            eo_contract<1, false>(uv, s2, tab.Bf);
+            T* so = Ra + el * RA + iz * QQ + qx;
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
-                T s0 = T(0), s1 = T(0), s2 = T(0);
-#pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    s0 = fma(vv[i], tab.B[i * Q + k], s0);   // d/dxi
-                    s1 = fma(uv[i], tab.G[i * Q + k], s1);   // d/deta
-                    s2 = fma(uv[i], tab.B[i * Q + k], s2);   // value (for d/dzeta)
-                }
-                so[k * Q] = s0;
-                so[D * QQ + k * Q] = s1;
-                so[2 * D * QQ + k * Q] = s2;
+                so[k * Q] = s0[k];
+                so[D * QQ + k * Q] = s1[k];
+                so[2 * D * QQ + k * Q] = s2[k];
             }
         }
         __syncthreads();
         // ---- forward Z: the thread's own (qx,qy) column
         if (has_col) {
-            const T* si = Ss + cel * SS + cq;
-#pragma unroll
-            for (int k = 0; k < Q; ++k) { gq[c][0][k] = T(0); gq[c][1][k] = T(0); gq[c][2][k] = T(0); }
+            const T* si = Ra + cel * RA + cq;
+            T i0[D], i1[D], i2[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                const T s0 = si[i * QQ], s1 = si[D * QQ + i * QQ], s2 = si[2 * D * QQ + i * QQ];
-#pragma unroll
-                for (int k = 0; k < Q; ++k) {
-                    gq[c][0][k] = fma(s0, tab.B[i * Q + k], gq[c][0][k]);
-                    gq[c][1][k] = fma(s1, tab.B[i * Q + k], gq[c][1][k]);
-                    gq[c][2][k] = fma(s2, tab.G[i * Q + k], gq[c][2][k]);
-                }
+                i0[i] = si[i * QQ];
+                i1[i] = si[D * QQ + i * QQ];
+                i2[i] = si[2 * D * QQ + i * QQ];
             }
+            eo_contract<1, false>(i0, gq[c][0], tab.Bf);
+            eo_contract<1, false>(i1, gq[c][1], tab.Bf);
+            eo_contract<-1, false>(i2, gq[c][2], tab.Gf);
         }
-        // the next X pass writes Us only; Ss is rewritten after the next barrier
     }
 
     // ---- pointwise stage: Voigt stress and Q = sigma J^{-T}, in place
     if (has_col) {
-        const int e = e0 + cel;
         T Ji[9], lw = T(0), mw = T(0);
-        if (e < g.NE) {
-            const T* d = ed + (size_t)e * kEdStride;
+        if (ebase[cel] >= 0) {
+            const T* d = ed + (size_t)(e0 + cel) * kEdStride;
 #pragma unroll
             for (int k = 0; k < 9; ++k) Ji[k] = d[k];
             lw = d[9];
@@ -202,8 +361,7 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __restrict_
         for (int k = 0; k < Q; ++k) {
             const T W = wxy * tab.w[k];
             const T lam = W * lw, mu = W * mw;
-            // physical gradient du[c][i] = d u_c / d x_i = sum_m Jinv[m][i] * ref[c][m]
-            T du[3][3];
+            T du[3][3];   // du[c][i] = d u_c / d x_i = sum_m Jinv[m][i] ref[c][m]
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
@@ -219,7 +377,6 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __restrict_
             s[0][1] = s[1][0] = mu * (du[0][1] + du[1][0]);
             s[0][2] = s[2][0] = mu * (du[0][2] + du[2][0]);
             s[1][2] = s[2][1] = mu * (du[1][2] + du[2][1]);
-            // Q_{c,m} = sum_i sigma_{c,i} Jinv[m][i]
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
@@ -228,88 +385,132 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __restrict_
         }
     }
 
-    // ---- backward sweeps, one output component at a time
+    // ---- backward sweeps and scatter, one output component at a time
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        // backward Z: column -> Ss[el][m][iz][qy][qx]
+        __syncthreads();   // previous component's scatter done with Ra
+        // backward Z: column -> Ra[el][m][iz][qy][qx]
         if (has_col) {
-            T* so = Ss + cel * SS + cq;
+            T t0[D], t1[D], t2[D];
+            eo_contract<1, false>(gq[c][0], t0, tab.Bt);
+            eo_contract<1, false>(gq[c][1], t1, tab.Bt);
+            eo_contract<-1, false>(gq[c][2], t2, tab.Gt);
+            T* so = Ra + cel * RA + cq;
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                T t0 = T(0), t1 = T(0), t2 = T(0);
-#pragma unroll
-                for (int k = 0; k < Q; ++k) {
-                    t0 = fma(gq[c][0][k], tab.B[i * Q + k], t0);
-                    t1 = fma(gq[c][1][k], tab.B[i * Q + k], t1);
-                    t2 = fma(gq[c][2][k], tab.G[i * Q + k], t2);
-                }
-                so[i * QQ] = t0;
-                so[D * QQ + i * QQ] = t1;
-                so[2 * D * QQ + i * QQ] = t2;
+                so[i * QQ] = t0[i];
+                so[D * QQ + i * QQ] = t1[i];
+                so[2 * D * QQ + i * QQ] = t2[i];
             }
         }
         __syncthreads();
-        // backward Y: lines (el, iz, qx): R0 = sum_qy T0 B, R12 = sum_qy (T1 G + T2 B)
+        // backward Y: lines (el, iz, qx): R0 = T0 B^T, R12 = T1 G^T + T2 B^T
         for (int w = tid; w < E * D * Q; w += NT) {
             const int el = w / (D * Q), r = w % (D * Q);
             const int iz = r / Q, qx = r % Q;
-            const T* ti = Ss + el * SS + iz * QQ + qx;
-            T t0[Q], t1[Q], t2[Q];
+            const T* ti = Ra + el * RA + iz * QQ + qx;
+            T a0[Q], a1[Q], a2[Q], r0[D], r12[D];
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
-                t0[k] = ti[k * Q];
-                t1[k] = ti[D * QQ + k * Q];
-                t2[k] = ti[2 * D * QQ + k * Q];
+                a0[k] = ti[k * Q];
+                a1[k] = ti[D * QQ + k * Q];
+                a2[k] = ti[2 * D * QQ + k * Q];
             }
-            T* ro = Us + el * US + iz * D * Q + qx;
+            eo_contract<1, false>(a0, r0, tab.Bt);
+            eo_contract2<-1, 1>(a1, tab.Gt, a2, tab.Bt, r12);
+            T* ro = Ua + el * UT + iz * D * QP + qx;
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                T r0 = T(0), r12 = T(0);
-#pragma unroll
-                for (int k = 0; k < Q; ++k) {
-                    r0 = fma(t0[k], tab.B[i * Q + k], r0);
-                    r12 = fma(t1[k], tab.G[i * Q + k], r12);
-                    r12 = fma(t2[k], tab.B[i * Q + k], r12);
-                }
-                ro[i * Q] = r0;
-                ro[D * D * Q + i * Q] = r12;
+                ro[i * QP] = r0[i];
+                ro[D * D * QP + i * QP] = r12[i];
             }
         }
         __syncthreads();
-        // backward X: lines (el, iz, iy): y(ix) = sum_qx R0 G + R12 B  -> Xs (output tile)
+        // backward X: lines (el, iz, iy): y = R0 G^T + R12 B^T -> Ra output tile (row stride DP)
         for (int w = tid; w < E * D * D; w += NT) {
             const int el = w / (D * D), r = w % (D * D);
-            const T* ri = Us + el * US + r * Q;
-            T r0[Q], r12[Q];
+            const T* ri = Ua + el * UT + r * QP;
+            T a0[Q], a1[Q], yo[D];
 #pragma unroll
-            for (int k = 0; k < Q; ++k) { r0[k] = ri[k]; r12[k] = ri[D * D * Q + k]; }
-            T* yo = Xs + el * XS + c * D3 + r * D;
+            for (int k = 0; k < Q; ++k) { a0[k] = ri[k]; a1[k] = ri[D * D * QP + k]; }
+            eo_contract2<-1, 1>(a0, tab.Gt, a1, tab.Bt, yo);
+            T* dst = Ra + el * RA + r * DP;
 #pragma unroll
-            for (int i = 0; i < D; ++i) {
-                T acc = T(0);
-#pragma unroll
-                for (int k = 0; k < Q; ++k) {
-                    acc = fma(r0[k], tab.G[i * Q + k], acc);
-                    acc = fma(r12[k], tab.B[i * Q + k], acc);
-                }
-                yo[i] = acc;
+            for (int i = 0; i < D; ++i) dst[i] = yo[i];
+        }
+        __syncthreads();
+        // scatter component c: interior nodes -> y (sole owner); skeleton nodes -> sk
+        for (int w = tid; w < E * D * D * D; w += NT) {
+            const int el = SK::ELEM_MAJOR ? w / (D * D * D) : w % E;
+            const int a = SK::ELEM_MAJOR ? w % (D * D * D) : w / E;
+            const int b = ebase[el];
+            if (b < 0) continue;
+            const int ix = a % D, iy = (a / D) % D, iz = a / (D * D);
+            const T v = Ra[el * RA + (iz * D + iy) * DP + ix];
+            if (SK::interior(ix, iy, iz)) {
+                T* yp = y + c * NN + b + ix + g.Nx * (iy + g.Ny * iz);
+                *yp = add ? *yp + v : v;
+            } else {
+                sk[SK::offset(e0 + el, c, SK::index(ix, iy, iz), g.NE)] = v;
             }
         }
-        // next component's backward Z writes Ss only (last read before the barrier above)
     }
-    __syncthreads();
+}
 
-    // ---- scatter-add (G^T)
-    for (int w = tid; w < E * XS; w += NT) {
-        const int el = w / XS, r = w % XS;
-        const int e = e0 + el;
-        if (e >= g.NE) continue;
-        const int c = r / D3, a = r % D3;
-        const int ix = a % D, iy = (a / D) % D, iz = a / (D * D);
-        const int ex = e % g.nx, ey = (e / g.nx) % g.ny, ez = e / (g.nx * g.ny);
-        const int gx = ex * P + ix, gy = ey * P + iy, gz = ez * P + iz;
-        if (clamped_node(g.clamp, gx, gy, gz, g)) continue;
-        atomic_add(y + (size_t)c * g.Nn + gx + g.Nx * (gy + g.Ny * gz), Xs[w]);
+// Kernel 2: for every element-boundary node, sum the skeleton contributions of its
+// elements in a fixed order (x-, then y-, then z-neighbour order) and write y.
+template <int P, typename T>
+__global__ void __launch_bounds__(256)
+pa_skeleton_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ sk, const Geom g, const int add) {
+    using SK = Skel<P + 1>;
+    const int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= g.Nn) return;
+    const int gx = node % g.Nx, r = node / g.Nx;
+    const int gy = r % g.Ny, gz = r / g.Ny;
+    const int rx = gx % P, ry = gy % P, rz = gz % P;
+    if (rx != 0 && ry != 0 && rz != 0) return;   // interior node: written by its element
+    // Per axis two candidate (element, local index) pairs: the element before the node
+    // (local index P) and the element containing it from the left (local index 0); a
+    // node strictly inside an element along the axis has one (valid) candidate.
+    int e_[3][2], l_[3][2];
+    bool v_[3][2];
+    const int gg[3] = {gx, gy, gz}, rr[3] = {rx, ry, rz}, nn[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int q = gg[a] / P;
+        if (rr[a] != 0) {
+            e_[a][0] = q; l_[a][0] = rr[a]; v_[a][0] = true;
+            e_[a][1] = q; l_[a][1] = rr[a]; v_[a][1] = false;
+        } else {
+            e_[a][0] = q - 1; l_[a][0] = P; v_[a][0] = q > 0;
+            e_[a][1] = q; l_[a][1] = 0; v_[a][1] = q < nn[a];
+        }
+    }
+    const size_t NN = (size_t)g.Nn;
+    const bool cl = g.clamp && clamped_node(g.clamp, gx, gy, gz, g);
+    T acc[3] = {T(0), T(0), T(0)};
+    if (!cl) {
+        // fixed summation order (z, y, x candidates), all loads independent
+#pragma unroll
+        for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+            for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+                for (int kx = 0; kx < 2; ++kx) {
+                    if (!(v_[0][kx] && v_[1][ky] && v_[2][kz])) continue;
+                    const int e = e_[0][kx] + g.nx * (e_[1][ky] + g.ny * e_[2][kz]);
+                    const int s = SK::index(l_[0][kx], l_[1][ky], l_[2][kz]);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) acc[c] += sk[SK::offset(e, c, s, g.NE)];
+                }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] = x[c * NN + node];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T* yp = y + c * NN + node;
+        *yp = add ? *yp + acc[c] : acc[c];
     }
 }
 
@@ -317,10 +518,14 @@ template <int P, int Q, typename T>
 int launch_apply_typed(const ApplyLaunch& L) {
     using C = ApplyCfg<P, Q, T>;
     if (L.g.NE == 0) return PA_OK;
-    const Tab1D<T, P + 1, Q> tab = make_tab<T, P + 1, Q>(*L.tab);
+    const ApplyTabs<T, P + 1, Q> tab = make_tabs<T, P + 1, Q>(*L.tab);
     const int nb = (L.g.NE + C::E - 1) / C::E;
-    hipLaunchKernelGGL((pa_apply_kernel<P, Q, T>), dim3(nb), dim3(C::NT), 0, L.stream,
-                       (const T*)L.x, (T*)L.y, (const T*)L.ed, tab, L.g);
+    hipLaunchKernelGGL((pa_apply_kernel<P, Q, T>), dim3(nb), dim3(C::NT), 0, L.stream, (const T*)L.x, (T*)L.y,
+                       (T*)L.sk, (const T*)L.ed, tab, L.g, L.add);
+    PA_HIP(hipGetLastError());
+    const int nb2 = (L.g.Nn + 255) / 256;
+    hipLaunchKernelGGL((pa_skeleton_kernel<P, T>), dim3(nb2), dim3(256), 0, L.stream, (const T*)L.x, (T*)L.y,
+                       (const T*)L.sk, L.g, L.add);
     PA_HIP(hipGetLastError());
     return PA_OK;
 }

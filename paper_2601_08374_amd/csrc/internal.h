@@ -56,6 +56,7 @@ struct ApplyLaunch {
     Geom g;
     const void* x;
     void* y;
+    void* sk;            // skeleton buffer of the operator (element-boundary contributions)
     const void* ed;      // per-element data of the launch dtype
     const Tables* tab;
     int add;             // accumulate into y (y pre-initialised by the caller)
@@ -71,6 +72,12 @@ int launch_apply_p5(const ApplyLaunch&, int q_off, int dtype);
 int launch_apply_p6(const ApplyLaunch&, int q_off, int dtype);
 int launch_apply_p7(const ApplyLaunch&, int q_off, int dtype);
 int launch_apply_p8(const ApplyLaunch&, int q_off, int dtype);
+
+// Words of the skeleton buffer of one operator: 3 components x element-boundary nodes per element.
+inline int64_t skeleton_words(int p, int64_t NE) {
+    const int64_t D = p + 1;
+    return NE * 3 * (D * D * D - (D - 2) * (D - 2) * (D - 2));
+}
 
 inline Geom make_geom(const MeshDesc& m, int p, bool constrained) {
     Geom g;
@@ -92,6 +99,7 @@ struct pa_op {
     hipStream_t stream = nullptr;
     std::vector<double> lam, mu;     // host copies (used to build solver hierarchies)
     void* ed = nullptr;              // device per-element data [NE][kEdStride] of dtype
+    void* sk = nullptr;              // skeleton buffer [NE][3][S] of dtype used by every apply
     double* d_tab = nullptr;         // device copy of the FP64 tables (B, G, w, bb/bg/gg, sB)
     double* d_vert = nullptr;        // device vertex coordinates, x | y | z
     pa::Tables tab;                  // host copy of the tables (kernel arguments)
