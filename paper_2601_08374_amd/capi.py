@@ -10,7 +10,8 @@ import ctypes as C
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "lib", "libpaelast.so")
+# PAELAST_LIB selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("PAELAST_LIB") or os.path.join(_PKG, "lib", "libpaelast.so")
 
 PA_OK = 0
 PA_EINVAL = -1

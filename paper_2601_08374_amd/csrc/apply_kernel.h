@@ -3,29 +3,31 @@
 // Kernel 1 (pa_apply_kernel), per element and per displacement component c
 // (paper Sec. 4.2 macro-kernel fusion, Sec. 4.4 sum factorization, Sec. 4.5
 // Voigt stress and transposed sweeps):
-//   gather x_c (restriction G, clamped entries read as 0)   -> LDS [D][D][D]
-//   forward X:  u = x B, v = x G        (lines (iz,iy))      -> LDS [2][D][D][Q]
-//   forward Y:  (v B, u G, u B)         (lines (iz,qx))      -> LDS [3][D][Q][Q]
+//   forward X:  u = x B, v = x G on lines (iz,iy) read straight from the
+//               L-vector (restriction G; clamped entries read as 0)  -> LDS [2][D][D][Q]
+//   forward Y:  (v B, u G, u B)         (lines (iz,qx))               -> LDS [3][D][Q][Q]
 //   forward Z:  into a register column per (qx,qy): ref-gradient [c][m][qz]
 // then pointwise, in registers: grad = J^{-T} ref-grad, Voigt stress with the
 // weighted w*detJ*lambda, w*detJ*mu (eq. 7), Q_{c,m} = sum_i sigma_{c,i} J^{-1}_{m,i};
-// then per output component: backward Z (column -> LDS), Y, X (the m-channels
-// that share a 1D factor are summed before the next sweep), and the scatter:
-// nodes strictly inside the element are written to y by their only owner;
-// element-boundary ("skeleton") contributions go to a per-element buffer.
+// then per output component: backward Z (column -> LDS), Y (-> LDS), X on
+// lines (iz,iy) (the m-channels that share a 1D factor are summed before the
+// next sweep), whose results go straight out: nodes strictly inside the element
+// are written to y by their only owner; element-boundary ("skeleton")
+// contributions go to a per-element buffer.
 // Kernel 2 (pa_skeleton_kernel) sums, for every element-boundary node, the
 // contributions of its (up to 8) elements in a fixed order and writes y -- no
 // atomics, no separate initialisation of y, bitwise-reproducible results.
 //
-// Every 1D contraction uses the even-odd decomposition: on the symmetric
-// Gauss-Lobatto / Gauss-Legendre point sets B[i][k] = B[D-1-i][Q-1-k] and
-// G[i][k] = -G[D-1-i][Q-1-k], so pairs of outputs k, Q-1-k come from the sums
-// and differences of mirrored inputs with half-size tables (half the FMAs).
+// From p = 4 on every 1D contraction uses the even-odd decomposition: on the
+// symmetric Gauss-Lobatto / Gauss-Legendre point sets B[i][k] = B[D-1-i][Q-1-k]
+// and G[i][k] = -G[D-1-i][Q-1-k], so pairs of outputs k, Q-1-k come from the
+// sums and differences of mirrored inputs with half-size tables.
 //
-// gfx950 mapping: the even-odd tables are kernel arguments (kernarg segment), so
+// gfx950 mapping: the tables are kernel arguments (kernarg segment), so
 // contractions read them with scalar loads as wave-uniform SGPR operands; lanes
 // map to whole 1D lines (inputs in VGPRs, no per-FMA LDS traffic); LDS only
-// transposes between sweeps, with odd row strides against bank conflicts.
+// transposes between sweeps, with odd row strides against bank conflicts; the
+// x lines of component c+1 are loaded while component c is being contracted.
 // Several elements share a workgroup at low p to fill 64-wide wavefronts.
 #pragma once
 
@@ -201,13 +203,10 @@ template <int P, int Q, typename T>
 struct ApplyCfg {
     static constexpr int D = P + 1;
     static constexpr int QQ = Q * Q;
-    static constexpr int DP = D | 1;   // padded row strides (odd, in words)
-    static constexpr int QP = Q | 1;
-    static constexpr int XT = D * D * DP;                  // gather / output tile of one component
-    static constexpr int UT = 2 * D * D * QP;              // X-pass output (two channels)
-    static constexpr int ST = 3 * D * QQ;                  // Y-pass output (three channels)
-    static constexpr int RA = ST > XT ? ST : XT;           // region shared by the tile and the Y output
-    static constexpr int LDS_ELEM = RA + UT;
+    static constexpr int QP = Q | 1;                 // padded (odd) row stride, in words
+    static constexpr int UT = 2 * D * D * QP;        // X-pass output (two channels) | backward Y output
+    static constexpr int ST = 3 * D * QQ;            // Y-pass output (three channels) | backward Z output
+    static constexpr int LDS_ELEM = ST + UT + kEdStride;
     static constexpr int pickE() {
         int bestE = 1;
         double bestU = 0.0;
@@ -239,17 +238,17 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
     using C = ApplyCfg<P, Q, T>;
     using SK = Skel<P + 1>;
     constexpr int D = P + 1, E = C::E, NT = C::NT, QQ = Q * Q;
-    constexpr int DP = C::DP, QP = C::QP;
-    constexpr int XT = C::XT, UT = C::UT, RA = C::RA;
-    constexpr int S = SK::S;
-    __shared__ T Ra[E * RA];     // gather tile | Y-pass output | backward Z output | output tile
-    __shared__ T Ua[E * UT];     // X-pass output | backward Y output
-    __shared__ int ebase[E];     // first node of each element, or -1 past the end
+    constexpr int QP = C::QP, UT = C::UT, ST = C::ST;
+    __shared__ T Ra[E * ST];          // Y-pass output | backward Z output
+    __shared__ T Ua[E * UT];          // X-pass output | backward Y output
+    __shared__ T Es[E * kEdStride];   // per-element PA data of the block
+    __shared__ int ebase[E];          // first node of each element, or -1 past the end
     __shared__ int ecoord[E][3];
 
     const int tid = threadIdx.x;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int e0 = blk * E;
+    const int ne_blk = g.NE - e0 < E ? g.NE - e0 : E;
     if (tid < E) {
         const int e = e0 + tid;
         if (e < g.NE) {
@@ -263,6 +262,8 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
             ebase[tid] = -1;
         }
     }
+    for (int w = tid; w < E * kEdStride; w += NT)
+        Es[w] = w < ne_blk * kEdStride ? ed[(size_t)e0 * kEdStride + w] : T(0);
 
     const int cel = tid / QQ, cq = tid % QQ;
     const int cqx = cq % Q, cqy = cq / Q;
@@ -270,42 +271,64 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
     T gq[3][3][Q];   // [component][reference direction][qz]
     const size_t NN = (size_t)g.Nn;
 
+    // x-lines of this thread: line l = (el, iz, iy) of the block, l = tid + j*NT.
+    // The first node of each line is computed once; the loads of component c+1
+    // are issued right after the X sweep of component c.
+    constexpr int NL = E * D * D;
+    constexpr int GX = (NL + NT - 1) / NT;
+    static_assert(GX * D <= 32, "clamp mask bits");
+    int ln_node[GX];       // global node of (ix = 0) of the line, or -1
+    unsigned ln_cl = 0u;   // bit j*D + ix: clamped node (read as 0)
+    __syncthreads();       // ebase, ecoord, Es ready
+#pragma unroll
+    for (int j = 0; j < GX; ++j) {
+        ln_node[j] = -1;
+        const int l = tid + j * NT;
+        if (l < NL) {
+            const int el = l / (D * D), r = l % (D * D);
+            const int iz = r / D, iy = r % D;
+            const int b = ebase[el];
+            if (b >= 0) {
+                ln_node[j] = b + g.Nx * (iy + g.Ny * iz);
+                if (g.clamp) {
+#pragma unroll
+                    for (int ix = 0; ix < D; ++ix)
+                        if (clamped_node(g.clamp, ecoord[el][0] + ix, ecoord[el][1] + iy, ecoord[el][2] + iz, g))
+                            ln_cl |= 1u << (j * D + ix);
+                }
+            }
+        }
+    }
+    T xr[GX][D];
+    auto line_load = [&](int c) {
+#pragma unroll
+        for (int j = 0; j < GX; ++j)
+#pragma unroll
+            for (int ix = 0; ix < D; ++ix)
+                xr[j][ix] = (ln_node[j] >= 0 && !((ln_cl >> (j * D + ix)) & 1u)) ? x[c * NN + ln_node[j] + ix] : T(0);
+    };
+    line_load(0);
+
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        __syncthreads();   // ebase ready (c = 0) / previous Z pass done reading Ra
-        // ---- gather component c: Ra[el][iz][iy][ix] (row stride DP); at low p consecutive
-        // lanes take consecutive elements (contiguous in x), else consecutive local nodes
-        for (int w = tid; w < E * D * D * D; w += NT) {
-            const int el = SK::ELEM_MAJOR ? w / (D * D * D) : w % E;
-            const int a = SK::ELEM_MAJOR ? w % (D * D * D) : w / E;
-            const int ix = a % D, iy = (a / D) % D, iz = a / (D * D);
-            const int b = ebase[el];
-            T v = T(0);
-            if (b >= 0) {
-                bool cl = false;
-                if (g.clamp)
-                    cl = clamped_node(g.clamp, ecoord[el][0] + ix, ecoord[el][1] + iy, ecoord[el][2] + iz, g);
-                if (!cl) v = x[c * NN + b + ix + g.Nx * (iy + g.Ny * iz)];
-            }
-            Ra[el * RA + (iz * D + iy) * DP + ix] = v;
-        }
-        __syncthreads();
-        // ---- forward X: lines (el, iz, iy)
-        for (int w = tid; w < E * D * D; w += NT) {
-            const int el = w / (D * D), r = w % (D * D);
-            const T* xin = Ra + el * RA + r * DP;
-            T xv[D], u[Q], v[Q];
+        // ---- forward X from the x lines: Ua[el][ch][iz][iy][qx]
 #pragma unroll
-            for (int i = 0; i < D; ++i) xv[i] = xin[i];
-            eo_contract<1, false>(xv, u, tab.Bf);
-            eo_contract<-1, false>(xv, v, tab.Gf);
-            T* uo = Ua + el * UT + r * QP;
+        for (int j = 0; j < GX; ++j) {
+            const int l = tid + j * NT;
+            if (l < NL) {
+                const int el = l / (D * D), r = l % (D * D);
+                T u[Q], v[Q];
+                eo_contract<1, false>(xr[j], u, tab.Bf);
+                eo_contract<-1, false>(xr[j], v, tab.Gf);
+                T* uo = Ua + el * UT + r * QP;
 #pragma unroll
-            for (int k = 0; k < Q; ++k) {
-                uo[k] = u[k];
-                uo[D * D * QP + k] = v[k];
+                for (int k = 0; k < Q; ++k) {
+                    uo[k] = u[k];
+                    uo[D * D * QP + k] = v[k];
+                }
             }
         }
+        if (c < 2) line_load(c + 1);
         __syncthreads();
         // ---- forward Y: lines (el, iz, qx): s0 = v B (d/dxi), s1 = u G (d/deta), s2 = u B
         for (int w = tid; w < E * D * Q; w += NT) {
@@ -318,7 +341,7 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
             eo_contract<1, false>(vv, s0, tab.Bf);
             eo_contract<-1, false>(uv, s1, tab.Gf);
             eo_contract<1, false>(uv, s2, tab.Bf);
-            T* so = Ra + el * RA + iz * QQ + qx;
+            T* so = Ra + el * ST + iz * QQ + qx;
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
                 so[k * Q] = s0[k];
@@ -329,7 +352,7 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
         __syncthreads();
         // ---- forward Z: the thread's own (qx,qy) column
         if (has_col) {
-            const T* si = Ra + cel * RA + cq;
+            const T* si = Ra + cel * ST + cq;
             T i0[D], i1[D], i2[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
@@ -341,21 +364,16 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
             eo_contract<1, false>(i1, gq[c][1], tab.Bf);
             eo_contract<-1, false>(i2, gq[c][2], tab.Gf);
         }
+        // the next X sweep writes Ua only; Ra is rewritten after the next barrier
     }
 
     // ---- pointwise stage: Voigt stress and Q = sigma J^{-T}, in place
     if (has_col) {
-        T Ji[9], lw = T(0), mw = T(0);
-        if (ebase[cel] >= 0) {
-            const T* d = ed + (size_t)(e0 + cel) * kEdStride;
+        T Ji[9];
+        const T* d = Es + cel * kEdStride;
 #pragma unroll
-            for (int k = 0; k < 9; ++k) Ji[k] = d[k];
-            lw = d[9];
-            mw = d[10];
-        } else {
-#pragma unroll
-            for (int k = 0; k < 9; ++k) Ji[k] = T(0);
-        }
+        for (int k = 0; k < 9; ++k) Ji[k] = d[k];
+        const T lw = d[9], mw = d[10];
         const T wxy = tab.w[cqx] * tab.w[cqy];
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
@@ -385,17 +403,17 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
         }
     }
 
-    // ---- backward sweeps and scatter, one output component at a time
+    // ---- backward sweeps, one output component at a time; results leave from the X sweep
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        __syncthreads();   // previous component's scatter done with Ra
-        // backward Z: column -> Ra[el][m][iz][qy][qx]
+        // backward Z: own column -> Ra[el][m][iz][qy][qx] (the previous Y sweep finished
+        // reading Ra before the barrier that preceded the previous X sweep)
         if (has_col) {
             T t0[D], t1[D], t2[D];
             eo_contract<1, false>(gq[c][0], t0, tab.Bt);
             eo_contract<1, false>(gq[c][1], t1, tab.Bt);
             eo_contract<-1, false>(gq[c][2], t2, tab.Gt);
-            T* so = Ra + cel * RA + cq;
+            T* so = Ra + cel * ST + cq;
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 so[i * QQ] = t0[i];
@@ -408,7 +426,7 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
         for (int w = tid; w < E * D * Q; w += NT) {
             const int el = w / (D * Q), r = w % (D * Q);
             const int iz = r / Q, qx = r % Q;
-            const T* ti = Ra + el * RA + iz * QQ + qx;
+            const T* ti = Ra + el * ST + iz * QQ + qx;
             T a0[Q], a1[Q], a2[Q], r0[D], r12[D];
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
@@ -426,39 +444,36 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
             }
         }
         __syncthreads();
-        // backward X: lines (el, iz, iy): y = R0 G^T + R12 B^T -> Ra output tile (row stride DP)
-        for (int w = tid; w < E * D * D; w += NT) {
-            const int el = w / (D * D), r = w % (D * D);
-            const T* ri = Ua + el * UT + r * QP;
-            T a0[Q], a1[Q], yo[D];
+        // backward X on lines (el, iz, iy): y = R0 G^T + R12 B^T, written out directly:
+        // element-interior nodes to y (sole owner), boundary nodes to the skeleton buffer
 #pragma unroll
-            for (int k = 0; k < Q; ++k) { a0[k] = ri[k]; a1[k] = ri[D * D * QP + k]; }
-            eo_contract2<-1, 1>(a0, tab.Gt, a1, tab.Bt, yo);
-            T* dst = Ra + el * RA + r * DP;
+        for (int j = 0; j < GX; ++j) {
+            const int l = tid + j * NT;
+            if (l < NL && ln_node[j] >= 0) {
+                const int el = l / (D * D), r = l % (D * D);
+                const int iz = r / D, iy = r % D;
+                const T* ri = Ua + el * UT + r * QP;
+                T a0[Q], a1[Q], yo[D];
 #pragma unroll
-            for (int i = 0; i < D; ++i) dst[i] = yo[i];
-        }
-        __syncthreads();
-        // scatter component c: interior nodes -> y (sole owner); skeleton nodes -> sk
-        for (int w = tid; w < E * D * D * D; w += NT) {
-            const int el = SK::ELEM_MAJOR ? w / (D * D * D) : w % E;
-            const int a = SK::ELEM_MAJOR ? w % (D * D * D) : w / E;
-            const int b = ebase[el];
-            if (b < 0) continue;
-            const int ix = a % D, iy = (a / D) % D, iz = a / (D * D);
-            const T v = Ra[el * RA + (iz * D + iy) * DP + ix];
-            if (SK::interior(ix, iy, iz)) {
-                T* yp = y + c * NN + b + ix + g.Nx * (iy + g.Ny * iz);
-                *yp = add ? *yp + v : v;
-            } else {
-                sk[SK::offset(e0 + el, c, SK::index(ix, iy, iz), g.NE)] = v;
+                for (int k = 0; k < Q; ++k) { a0[k] = ri[k]; a1[k] = ri[D * D * QP + k]; }
+                eo_contract2<-1, 1>(a0, tab.Gt, a1, tab.Bt, yo);
+#pragma unroll
+                for (int ix = 0; ix < D; ++ix) {
+                    if (SK::interior(ix, iy, iz)) {
+                        T* yp = y + c * NN + ln_node[j] + ix;
+                        *yp = add ? *yp + yo[ix] : yo[ix];
+                    } else {
+                        sk[SK::offset(e0 + el, c, SK::index(ix, iy, iz), g.NE)] = yo[ix];
+                    }
+                }
             }
         }
+        // the next backward Z writes Ra only; Ua is rewritten after the next barrier
     }
 }
 
 // Kernel 2: for every element-boundary node, sum the skeleton contributions of its
-// elements in a fixed order (x-, then y-, then z-neighbour order) and write y.
+// elements in a fixed order and write y.
 template <int P, typename T>
 __global__ void __launch_bounds__(256)
 pa_skeleton_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ sk, const Geom g, const int add) {
