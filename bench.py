@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the matrix-free PA elasticity apply (and, optionally, GMG-PCG solves).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--solve] [--serve N]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve] [--serve N]
 
 Workload (one GPU): the operator-apply sweep on the globally sheared box --
 (120/p,120/p,96/p) affine parallelepipeds (shear 0.2), ~4.2M dofs, q = p+2,
@@ -33,10 +33,23 @@ PEAK_F32_TFLOPS = 157.3    # MI355X vector FP32
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
 STEP_PS = (1, 2, 4, 6, 8)
 
-# HBM traffic of the apply kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
-# (KiB per dispatch, scaled by the copy-kernel calibration factor), keyed by the
-# source hash of the kernel they were measured on.  Empty until measured.
-MEASURED_TRAFFIC = {}
+# HBM bytes per FP64 apply (apply kernel + skeleton kernel) from two rocprofv3
+# --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).  Each counter is
+# scaled by what it reads for a 256 MiB device-to-device copy: FETCH_SIZE reads
+# 131088 KiB (factor 2.0), WRITE_SIZE 262144 KiB (factor 1.0).  Keyed by the
+# source hash of the kernels they were taken on, so an edited kernel reports
+# null until it is measured again.
+MEASURED_TRAFFIC = {
+    ("6afa840833be3923", 1, "f64"): 776213882,
+    ("6afa840833be3923", 2, "f64"): 339713005,
+    ("6afa840833be3923", 4, "f64"): 289751770,
+    ("6afa840833be3923", 8, "f64"): 178265930,
+}
+
+
+def log(msg: str):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def flops_per_element(p: int, q: int | None = None) -> int:
@@ -54,7 +67,7 @@ def algorithmic_bytes(N: int, NE: int, word: int) -> int:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("apply_kernel.h", "vec.hip"):
+    for f in ("apply_kernel.h",):
         with open(os.path.join(ROOT, "paper_2601_08374_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -97,13 +110,14 @@ def cpu_baseline(ps, budget_s: float = 25.0):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--rotate-gb", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
-    ap.add_argument("--solve", action="store_true", help="also time the cantilever GMG-PCG solves")
-    ap.add_argument("--serve", type=int, default=0, help="also run a serving stream of this many requests")
+    ap.add_argument("--no-solve", action="store_true", help="skip the cantilever GMG-PCG solves")
+    ap.add_argument("--serve", type=int, default=512,
+                    help="requests in the serving stream (0 skips it)")
     ap.add_argument("--profile-apply", type=int, default=0, metavar="P",
                     help="profiling mode: only run --reps applies of the degree-P sheared-box operator "
                          "(then three 256 MiB copies that calibrate the traffic counters) and exit")
@@ -184,6 +198,7 @@ def main(argv=None):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     per_p_ms = {p: float(np.mean([a.elapsed_time(b) for a, b in events[p]])) for p in STEP_PS}
+    log(f"timed step done: {args.steps} steps in {wall:.3f} s")
     total_dofs = args.steps * sum(setups[p]["N"] for p in STEP_PS)
     value = total_dofs / wall / 1e9
 
@@ -225,6 +240,7 @@ def main(argv=None):
     if not args.no_sweep:
         sweep = {}
         for p in range(1, 9):
+            log(f"sweep p={p}")
             sweep[p] = {}
             for dtype, name, peak in ((pa.PA_F64, "f64", PEAK_F64_TFLOPS), (pa.PA_F32, "f32", PEAK_F32_TFLOPS)):
                 s = make(p, dtype)
@@ -258,14 +274,17 @@ def main(argv=None):
                 torch.cuda.empty_cache()
         result["sweep"] = sweep
 
-    if args.solve:
+    if not args.no_solve:
+        log("cantilever solves")
         from paper_2601_08374_amd import benchmarks
         result["solve"] = benchmarks.cantilever_solves(torch, dev)
     if args.serve:
+        log(f"serving stream of {args.serve} requests")
         from paper_2601_08374_amd import serve
         result["serve"] = serve.bench_stream(args.serve)
 
     if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(STEP_PS)
     print(json.dumps(result), flush=True)
     return 0

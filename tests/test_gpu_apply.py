@@ -203,3 +203,28 @@ def test_full_size_sheared_box_sampled(p, dtype):
         u[c * Nn:(c + 1) * Nn] = 1
         r = op.apply(u, flags=pa.PA_UNCONSTRAINED)
         assert float(torch.linalg.norm(r)) <= 10 * TOL[dtype] * nrm * float(torch.linalg.norm(u))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 8])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_apply_bitwise_reproducible(p, dtype):
+    """The assembly of element contributions has a fixed summation order (no atomics): repeated
+    applies are bitwise identical, and the overwrite form ignores what the output held before."""
+    pa = _pa()
+    print(f"bitwise reproducibility p={p} dtype={dtype}", flush=True)
+    mesh = _case_mesh(p, seed=p)
+    NE = mesh.num_elements
+    rng = np.random.default_rng(200 + p)
+    lam, mu = rng.uniform(0.2, 3.0, NE), rng.uniform(0.2, 3.0, NE)
+    op = pa.Operator(mesh, p, lam, mu, q=p + 2, dtype=dtype)
+    tdt = torch.float64 if dtype == pa.PA_F64 else torch.float32
+    xt = torch.tensor(syn.uniform_vector(op.N, seed=p), dtype=tdt, device="cuda")
+    outs = []
+    for fill in (0.0, float("nan"), 1e30):
+        y = torch.full((op.N,), fill, dtype=tdt, device="cuda")
+        op.apply(xt, y)
+        outs.append(y)
+    torch.cuda.synchronize()
+    for y in outs[1:]:
+        assert torch.equal(y, outs[0])
+    assert bool(torch.isfinite(outs[0]).all())
