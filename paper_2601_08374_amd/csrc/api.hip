@@ -93,7 +93,7 @@ int create_op(const MeshDesc& md, int p, int q, const double* lam, const double*
         if (rc) break;
         if (hipMalloc(&op->d_vert, nvert * sizeof(double)) != hipSuccess ||
             hipMalloc(&op->ed, (size_t)NE * kEdStride * esz) != hipSuccess ||
-            hipMalloc(&op->sk, (size_t)skeleton_words(p, NE) * esz) != hipSuccess ||
+            hipMalloc(&op->sk, (size_t)skeleton_words(p, md.n) * esz) != hipSuccess ||
             hipMalloc(&d_lm, 2 * (size_t)NE * sizeof(double)) != hipSuccess) {
             (void)hipGetLastError();
             rc = fail(PA_ENOMEM, "device allocation failed (%lld elements)", (long long)NE);

@@ -1,6 +1,414 @@
-// Fused apply instantiations for polynomial degree p = 1 (q = p+1, p+2, p+3; FP64 and FP32).
+// Apply for linear elements (p = 1): register-resident, one lane per element.
+//
+// The steps are those of the fused kernel (paper Sec. 4.2, 4.4, 4.5): forward
+// X/Y/Z sum-factorization sweeps to the reference gradient, pointwise Voigt
+// stress with w*detJ*lambda, w*detJ*mu and Q = sigma J^{-T} (eq. 7), transposed
+// sweeps back to the nodes.  With two nodes per axis the whole element state
+// fits in registers, so each lane runs them for its own element with loops
+// over the quadrature points: no LDS, no barriers.  The derivative of the
+// linear Lagrange basis on [0,1] is -1 and +1 at every point, so every
+// derivative contraction is a difference.
+//
+// A wavefront is a tile of kLinTX x kLinTY element columns (lane = column);
+// each lane walks kLinTZ elements up its column, carrying the upper face of
+// one element (x values and partial results) in registers into the next, and
+// prefetching the next element's x face and PA data while it computes.  After
+// each element the finished node layer is summed across lanes with shuffles
+// (x neighbour, then y neighbour); every node of the layer has one owning
+// lane, which writes y itself when all elements touching the node lie in the
+// tile, and otherwise stores its partial sum in the tile's slot of the
+// skeleton buffer.  pa_lin_skeleton_kernel then adds the (up to 8) tile
+// partial sums of every tile-boundary node in a fixed order: no atomics,
+// bitwise-reproducible results.
 #include "apply_kernel.h"
 
 namespace pa {
-int launch_apply_p1(const ApplyLaunch& L, int q_off, int dtype) { return launch_apply_p<1>(L, q_off, dtype); }
+
+template <typename T, int Q>
+struct LinTabs {
+    T B0[Q], B1[Q];   // linear Lagrange basis at the Gauss-Legendre points: 1 - xi_k, xi_k
+    T w[Q];           // Gauss-Legendre weights on [0,1]
+    T wzy[Q * Q];     // w[qz] * w[qy]
+};
+
+// 12 words of per-element data with 16-byte loads (the rows are 48 or 96 bytes).
+__device__ __forceinline__ void load_ed12(const double* p, double (&d)[12]) {
+    const double2* v = reinterpret_cast<const double2*>(p);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const double2 t = v[i];
+        d[2 * i] = t.x;
+        d[2 * i + 1] = t.y;
+    }
+}
+__device__ __forceinline__ void load_ed12(const float* p, float (&d)[12]) {
+    const float4* v = reinterpret_cast<const float4*>(p);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float4 t = v[i];
+        d[4 * i] = t.x;
+        d[4 * i + 1] = t.y;
+        d[4 * i + 2] = t.z;
+        d[4 * i + 3] = t.w;
+    }
+}
+
+// Slot of node (lx, ly, lz) of tile t (local node coordinates in the tile's node box).
+__device__ __forceinline__ size_t lin_slot(int t, int c, int lz, int ly, int lx) {
+    return (((size_t)t * 3 + c) * (kLinTZ + 1) + lz) * ((kLinTY + 1) * (kLinTX + 1)) + ly * (kLinTX + 1) + lx;
+}
+
+// Element contribution y_e = K_e x_e of one element, added to ya (lower face iz = 0)
+// and yb (upper face iz = 1).  Arrays are [component][iy][ix].
+template <int Q, typename T>
+__device__ __forceinline__ void lin_element(const T (&xa)[3][2][2], const T (&xb)[3][2][2], const T (&d)[12],
+                                            const LinTabs<T, Q>& tb, T (&ya)[3][2][2], T (&yb)[3][2][2]) {
+    T Ji[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Ji[k] = d[k];
+    const T lw = d[9], mw = d[10];
+    T dz[3][2][2], U2[3][2][2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int iy = 0; iy < 2; ++iy)
+#pragma unroll
+            for (int ix = 0; ix < 2; ++ix) {
+                dz[c][iy][ix] = xb[c][iy][ix] - xa[c][iy][ix];
+                U2[c][iy][ix] = T(0);
+            }
+#pragma unroll 1
+    for (int qz = 0; qz < Q; ++qz) {
+        const T bz0 = tb.B0[qz], bz1 = tb.B1[qz];
+        T xz[3][2][2], t0[3][2][2], t2[3][2][2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int iy = 0; iy < 2; ++iy)
+#pragma unroll
+                for (int ix = 0; ix < 2; ++ix) {
+                    xz[c][iy][ix] = bz0 * xa[c][iy][ix] + bz1 * xb[c][iy][ix];
+                    t0[c][iy][ix] = T(0);
+                    t2[c][iy][ix] = T(0);
+                }
+#pragma unroll 1
+        for (int qy = 0; qy < Q; ++qy) {
+            const T by0 = tb.B0[qy], by1 = tb.B1[qy];
+            const T wzy = tb.wzy[qz * Q + qy];
+            const T lzy = lw * wzy, mzy = mw * wzy;
+            // forward Y: a = B_y B_z x, b = G_y B_z x, e = B_y G_z x on the two x-columns ix
+            T a[3][2], b[3][2], e[3][2];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int ix = 0; ix < 2; ++ix) {
+                    a[c][ix] = by0 * xz[c][0][ix] + by1 * xz[c][1][ix];
+                    b[c][ix] = xz[c][1][ix] - xz[c][0][ix];
+                    e[c][ix] = by0 * dz[c][0][ix] + by1 * dz[c][1][ix];
+                }
+            T S0[3], r1[3][2], r2[3][2];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                S0[c] = T(0);
+                r1[c][0] = r1[c][1] = r2[c][0] = r2[c][1] = T(0);
+            }
+#pragma unroll
+            for (int qx = 0; qx < Q; ++qx) {
+                const T bx0 = tb.B0[qx], bx1 = tb.B1[qx];
+                // forward X: reference gradient g[c][m] at (qx, qy, qz)
+                T g[3][3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    g[c][0] = a[c][1] - a[c][0];
+                    g[c][1] = bx0 * b[c][0] + bx1 * b[c][1];
+                    g[c][2] = bx0 * e[c][0] + bx1 * e[c][1];
+                }
+                const T lam = lzy * tb.w[qx], mu = mzy * tb.w[qx];
+                T du[3][3];   // du[c][i] = d u_c / d x_i = sum_m Jinv[m][i] g[c][m]
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+                        du[c][i] = Ji[0 * 3 + i] * g[c][0] + Ji[1 * 3 + i] * g[c][1] + Ji[2 * 3 + i] * g[c][2];
+                const T div = du[0][0] + du[1][1] + du[2][2];
+                const T ld = lam * div, m2 = mu + mu;
+                T s[3][3];
+                s[0][0] = ld + m2 * du[0][0];
+                s[1][1] = ld + m2 * du[1][1];
+                s[2][2] = ld + m2 * du[2][2];
+                s[0][1] = s[1][0] = mu * (du[0][1] + du[1][0]);
+                s[0][2] = s[2][0] = mu * (du[0][2] + du[2][0]);
+                s[1][2] = s[2][1] = mu * (du[1][2] + du[2][1]);
+                // Q[c][m] = sum_i sigma[c][i] Jinv[m][i]; backward X into (S0, r1, r2)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const T q0 = s[c][0] * Ji[0] + s[c][1] * Ji[1] + s[c][2] * Ji[2];
+                    const T q1 = s[c][0] * Ji[3] + s[c][1] * Ji[4] + s[c][2] * Ji[5];
+                    const T q2 = s[c][0] * Ji[6] + s[c][1] * Ji[7] + s[c][2] * Ji[8];
+                    S0[c] += q0;
+                    r1[c][0] += bx0 * q1;
+                    r1[c][1] += bx1 * q1;
+                    r2[c][0] += bx0 * q2;
+                    r2[c][1] += bx1 * q2;
+                }
+            }
+            // backward Y: t0 += B_y (G_x channel) + G_y (channel 1), t2 += B_y (channel 2)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                t0[c][0][0] += -by0 * S0[c] - r1[c][0];
+                t0[c][0][1] += by0 * S0[c] - r1[c][1];
+                t0[c][1][0] += -by1 * S0[c] + r1[c][0];
+                t0[c][1][1] += by1 * S0[c] + r1[c][1];
+#pragma unroll
+                for (int ix = 0; ix < 2; ++ix) {
+                    t2[c][0][ix] += by0 * r2[c][ix];
+                    t2[c][1][ix] += by1 * r2[c][ix];
+                }
+            }
+        }
+        // backward Z: B_z for channels 0 and 1; the G_z channel is summed over qz first
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int iy = 0; iy < 2; ++iy)
+#pragma unroll
+                for (int ix = 0; ix < 2; ++ix) {
+                    ya[c][iy][ix] += bz0 * t0[c][iy][ix];
+                    yb[c][iy][ix] += bz1 * t0[c][iy][ix];
+                    U2[c][iy][ix] += t2[c][iy][ix];
+                }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int iy = 0; iy < 2; ++iy)
+#pragma unroll
+            for (int ix = 0; ix < 2; ++ix) {
+                ya[c][iy][ix] -= U2[c][iy][ix];
+                yb[c][iy][ix] += U2[c][iy][ix];
+            }
+}
+
+template <int Q, typename T>
+__global__ void __launch_bounds__(256)
+pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, const T* __restrict__ ed,
+                    const LinTabs<T, Q> tb, const Geom g, const int add) {
+    constexpr int TX = kLinTX, TY = kLinTY, TZ = kLinTZ;
+    static_assert(TX * TY == 64, "one tile per wavefront");
+    const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + TZ - 1) / TZ;
+    const int tile = xcd_block(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6);
+    if (tile >= ntx * nty * ntz) return;   // the whole wavefront leaves together
+    const int lane = threadIdx.x & 63;
+    const int lx = lane % TX, ly = lane / TX;
+    const int tx = tile % ntx, tr = tile / ntx;
+    const int ty = tr % nty, tz = tr / nty;
+    const int tx0 = tx * TX, ty0 = ty * TY, ez0 = tz * TZ;
+    const int tx1 = min(tx0 + TX, g.nx), ty1 = min(ty0 + TY, g.ny), ez1 = min(ez0 + TZ, g.nz);
+    const int ex = tx0 + lx, ey = ty0 + ly;
+    const bool valid = ex < g.nx && ey < g.ny;
+    const bool lastx = ex == tx1 - 1, lasty = ey == ty1 - 1;
+    const size_t NN = (size_t)g.Nn;
+
+    // clamped corner nodes of the column's faces are read as 0 (constrained operator)
+    auto load_face = [&](int gz, T (&f)[3][2][2]) {
+#pragma unroll
+        for (int iy = 0; iy < 2; ++iy)
+#pragma unroll
+            for (int ix = 0; ix < 2; ++ix) {
+                const int node = (ex + ix) + g.Nx * ((ey + iy) + g.Ny * gz);
+                const bool use = valid && !(g.clamp && clamped_node(g.clamp, ex + ix, ey + iy, gz, g));
+#pragma unroll
+                for (int c = 0; c < 3; ++c) f[c][iy][ix] = use ? x[c * NN + node] : T(0);
+            }
+    };
+    auto load_data = [&](int ez, T (&d)[12]) {
+        if (valid) {
+            load_ed12(ed + (size_t)(ex + g.nx * (ey + g.ny * ez)) * kEdStride, d);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) d[k] = T(0);
+        }
+    };
+    // sum node layer gz across lanes and write it: y for nodes whose elements all lie
+    // in the tile, the tile's skeleton slot for the others
+    auto emit_layer = [&](T (&v)[3][2][2], int gz) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int iy = 0; iy < 2; ++iy) {
+                const T t = __shfl_up(v[c][iy][1], 1, TX);
+                if (lx > 0) v[c][iy][0] += t;
+            }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int ix = 0; ix < 2; ++ix) {
+                const T t = __shfl_up(v[c][1][ix], TX, 64);
+                if (ly > 0) v[c][0][ix] += t;
+            }
+        if (!valid) return;
+        const bool cz = (gz > ez0 || gz == 0) && (gz < ez1 || gz == g.nz);
+#pragma unroll
+        for (int iy = 0; iy < 2; ++iy)
+#pragma unroll
+            for (int ix = 0; ix < 2; ++ix) {
+                if ((ix && !lastx) || (iy && !lasty)) continue;   // node owned by another lane
+                const int gx = ex + ix, gy = ey + iy;
+                const bool cx = (gx > tx0 || gx == 0) && (gx < tx1 || gx == g.nx);
+                const bool cy = (gy > ty0 || gy == 0) && (gy < ty1 || gy == g.ny);
+                if (cx && cy && cz) {
+                    const int node = gx + g.Nx * (gy + g.Ny * gz);
+                    const bool cl = g.clamp && clamped_node(g.clamp, gx, gy, gz, g);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const T val = cl ? x[c * NN + node] : v[c][iy][ix];
+                        T* yp = y + c * NN + node;
+                        *yp = add ? *yp + val : val;
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) sk[lin_slot(tile, c, gz - ez0, gy - ty0, gx - tx0)] = v[c][iy][ix];
+                }
+            }
+    };
+
+    T xa[3][2][2], xn[3][2][2], ya[3][2][2], dn[12];
+    load_face(ez0, xa);
+    load_face(ez0 + 1, xn);
+    load_data(ez0, dn);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int iy = 0; iy < 2; ++iy)
+#pragma unroll
+            for (int ix = 0; ix < 2; ++ix) ya[c][iy][ix] = T(0);
+#pragma unroll 1
+    for (int ez = ez0; ez < ez1; ++ez) {
+        T xb[3][2][2], d[12], yb[3][2][2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int iy = 0; iy < 2; ++iy)
+#pragma unroll
+                for (int ix = 0; ix < 2; ++ix) {
+                    xb[c][iy][ix] = xn[c][iy][ix];
+                    yb[c][iy][ix] = T(0);
+                }
+#pragma unroll
+        for (int k = 0; k < 12; ++k) d[k] = dn[k];
+        if (ez + 1 < ez1) {   // prefetch the next element of the column
+            load_face(ez + 2, xn);
+            load_data(ez + 1, dn);
+        }
+        lin_element<Q, T>(xa, xb, d, tb, ya, yb);
+        emit_layer(ya, ez);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int iy = 0; iy < 2; ++iy)
+#pragma unroll
+                for (int ix = 0; ix < 2; ++ix) {
+                    xa[c][iy][ix] = xb[c][iy][ix];
+                    ya[c][iy][ix] = yb[c][iy][ix];
+                }
+    }
+    emit_layer(ya, ez1);
+}
+
+// For every node on a tile boundary: sum the partial sums of the tiles touching it
+// in a fixed order (z, y, x candidates) and write y.
+template <typename T>
+__global__ void __launch_bounds__(256)
+pa_lin_skeleton_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ sk, const Geom g,
+                       const int add) {
+    const int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= g.Nn) return;
+    const int gx = node % g.Nx, r = node / g.Nx;
+    const int gy = r % g.Ny, gz = r / g.Ny;
+    const int gg[3] = {gx, gy, gz}, nn[3] = {g.nx, g.ny, g.nz}, TT[3] = {kLinTX, kLinTY, kLinTZ};
+    // per axis the tiles of the elements before (gg-1) and after (gg) the node
+    int t_[3][2];
+    bool v_[3][2];
+    bool single = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const bool lo = gg[a] > 0, hi = gg[a] < nn[a];
+        t_[a][0] = lo ? (gg[a] - 1) / TT[a] : 0;
+        t_[a][1] = hi ? gg[a] / TT[a] : 0;
+        v_[a][0] = lo;
+        v_[a][1] = hi && !(lo && t_[a][1] == t_[a][0]);
+        single = single && !(v_[a][0] && v_[a][1]);
+    }
+    if (single) return;   // every element of the node is in one tile: written by the apply kernel
+    const int ntx = (g.nx + kLinTX - 1) / kLinTX, nty = (g.ny + kLinTY - 1) / kLinTY;
+    const size_t NN = (size_t)g.Nn;
+    const bool cl = g.clamp && clamped_node(g.clamp, gx, gy, gz, g);
+    T acc[3] = {T(0), T(0), T(0)};
+    if (!cl) {
+#pragma unroll
+        for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+            for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+                for (int kx = 0; kx < 2; ++kx) {
+                    if (!(v_[0][kx] && v_[1][ky] && v_[2][kz])) continue;
+                    const int tx = t_[0][kx], ty = t_[1][ky], tz = t_[2][kz];
+                    const int t = tx + ntx * (ty + nty * tz);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        acc[c] += sk[lin_slot(t, c, gz - tz * kLinTZ, gy - ty * kLinTY, gx - tx * kLinTX)];
+                }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] = x[c * NN + node];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T* yp = y + c * NN + node;
+        *yp = add ? *yp + acc[c] : acc[c];
+    }
+}
+
+template <int Q, typename T>
+int launch_lin(const ApplyLaunch& L) {
+    const Geom& g = L.g;
+    if (g.NE == 0) return PA_OK;
+    if (L.tab->p != 1 || L.tab->q != Q) return fail(PA_EINVAL, "tables are for p=%d q=%d", L.tab->p, L.tab->q);
+    LinTabs<T, Q> tb;
+    for (int k = 0; k < Q; ++k) {
+        tb.B0[k] = (T)L.tab->B[0 * Q + k];
+        tb.B1[k] = (T)L.tab->B[1 * Q + k];
+        tb.w[k] = (T)L.tab->w[k];
+    }
+    for (int qz = 0; qz < Q; ++qz)
+        for (int qy = 0; qy < Q; ++qy) tb.wzy[qz * Q + qy] = (T)(L.tab->w[qz] * L.tab->w[qy]);
+    const int64_t nt = lin_tiles(g.nx, g.ny, g.nz);
+    const int nb = (int)((nt + 3) / 4);
+    hipLaunchKernelGGL((pa_apply_lin_kernel<Q, T>), dim3(nb), dim3(256), 0, L.stream, (const T*)L.x, (T*)L.y,
+                       (T*)L.sk, (const T*)L.ed, tb, g, L.add);
+    PA_HIP(hipGetLastError());
+    const int nb2 = (g.Nn + 255) / 256;
+    hipLaunchKernelGGL((pa_lin_skeleton_kernel<T>), dim3(nb2), dim3(256), 0, L.stream, (const T*)L.x, (T*)L.y,
+                       (const T*)L.sk, g, L.add);
+    PA_HIP(hipGetLastError());
+    return PA_OK;
+}
+
+int launch_apply_p1(const ApplyLaunch& L, int q_off, int dtype) {
+    if (dtype == PA_F64) {
+        switch (q_off) {
+            case 0: return launch_lin<2, double>(L);
+            case 1: return launch_lin<3, double>(L);
+            case 2: return launch_lin<4, double>(L);
+        }
+    } else {
+        switch (q_off) {
+            case 0: return launch_lin<2, float>(L);
+            case 1: return launch_lin<3, float>(L);
+            case 2: return launch_lin<4, float>(L);
+        }
+    }
+    return fail(PA_EUNSUPPORTED, "q = p+1+%d not built", q_off);
+}
+
 }  // namespace pa

@@ -73,8 +73,20 @@ int launch_apply_p6(const ApplyLaunch&, int q_off, int dtype);
 int launch_apply_p7(const ApplyLaunch&, int q_off, int dtype);
 int launch_apply_p8(const ApplyLaunch&, int q_off, int dtype);
 
-// Words of the skeleton buffer of one operator: 3 components x element-boundary nodes per element.
-inline int64_t skeleton_words(int p, int64_t NE) {
+// Linear elements (p = 1) run a register-resident kernel in which one wavefront
+// covers kLinTX x kLinTY element columns and each lane walks kLinTZ elements up
+// its column; only nodes on the faces of such tiles go through the skeleton buffer.
+constexpr int kLinTX = 8, kLinTY = 8, kLinTZ = 4;
+
+inline int64_t lin_tiles(int nx, int ny, int nz) {
+    return (int64_t)((nx + kLinTX - 1) / kLinTX) * ((ny + kLinTY - 1) / kLinTY) * ((nz + kLinTZ - 1) / kLinTZ);
+}
+
+// Words of the skeleton buffer of one operator: per element, 3 components x its
+// element-boundary nodes; for p = 1, 3 components x the node box of every tile.
+inline int64_t skeleton_words(int p, const int n[3]) {
+    if (p == 1) return lin_tiles(n[0], n[1], n[2]) * 3 * (kLinTX + 1) * (kLinTY + 1) * (kLinTZ + 1);
+    const int64_t NE = (int64_t)n[0] * n[1] * n[2];
     const int64_t D = p + 1;
     return NE * 3 * (D * D * D - (D - 2) * (D - 2) * (D - 2));
 }
@@ -99,7 +111,7 @@ struct pa_op {
     hipStream_t stream = nullptr;
     std::vector<double> lam, mu;     // host copies (used to build solver hierarchies)
     void* ed = nullptr;              // device per-element data [NE][kEdStride] of dtype
-    void* sk = nullptr;              // skeleton buffer [NE][3][S] of dtype used by every apply
+    void* sk = nullptr;              // skeleton buffer (skeleton_words) of dtype used by every apply
     double* d_tab = nullptr;         // device copy of the FP64 tables (B, G, w, bb/bg/gg, sB)
     double* d_vert = nullptr;        // device vertex coordinates, x | y | z
     pa::Tables tab;                  // host copy of the tables (kernel arguments)

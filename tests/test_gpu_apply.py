@@ -77,6 +77,26 @@ def test_apply_parity_all_orders(p, q, dtype):
         assert _rel(y, ref) <= TOL[dtype], (flags, _rel(y, ref))
 
 
+@pytest.mark.parametrize("q", [2, 3, 4])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_apply_p1_tiles(q, dtype):
+    """Linear elements: a mesh spanning several 8x8x4-element tiles with ragged tails on every
+    axis (interior, face, edge and corner nodes shared between tiles), clamped on three faces."""
+    pa = _pa()
+    print(f"p=1 tiles q={q} dtype={dtype}", flush=True)
+    mesh = syn.graded_mesh((19, 11, 9), seed=4, L=(1.9, 1.1, 0.9), A=syn.random_rotation(4) @ syn.SHEAR_A,
+                           clamped_faces=0b100101)
+    NE = mesh.num_elements
+    rng = np.random.default_rng(41)
+    lam, mu = rng.uniform(0.2, 3.0, NE), rng.uniform(0.2, 3.0, NE)
+    x = syn.uniform_vector(mesh.num_dofs(1), seed=5)
+    op_ref = elasticity.Operator(mesh, 1, q, lam, mu)
+    for flags, constrained in ((0, True), (1, False)):
+        ref = op_ref.apply(x, constrained=constrained)
+        y, _ = _gpu_apply(mesh, 1, q, lam, mu, x, dtype, flags=flags)
+        assert _rel(y, ref) <= TOL[dtype], (flags, _rel(y, ref))
+
+
 @pytest.mark.parametrize("dtype", [0, 1])
 def test_apply_add_flag_and_constrained_rows(dtype):
     pa = _pa()
