@@ -58,143 +58,201 @@ __device__ __forceinline__ size_t lin_slot(int t, int c, int lz, int ly, int lx)
     return (((size_t)t * 3 + c) * (kLinTZ + 1) + lz) * ((kLinTY + 1) * (kLinTX + 1)) + ly * (kLinTX + 1) + lx;
 }
 
-// Element contribution y_e = K_e x_e of one element, added to ya (lower face iz = 0)
-// and yb (upper face iz = 1).  Arrays are [component][iy][ix].
+// One (qy, qz) column of quadrature points: forward X to the reference gradient
+// g[c][m], pointwise stress and Q = sigma J^{-T} (weights w[qx] * lzy, mzy), and
+// backward X into S0 (G_x channel, summed over qx) and r1, r2 (B_x channels).
+// Inputs per component c and x-column ix: a = B_y B_z x, b = G_y B_z x, e = B_y G_z x.
 template <int Q, typename T>
-__device__ __forceinline__ void lin_element(const T (&xa)[3][2][2], const T (&xb)[3][2][2], const T (&d)[12],
-                                            const LinTabs<T, Q>& tb, T (&ya)[3][2][2], T (&yb)[3][2][2]) {
+__device__ __forceinline__ void lin_column(const T (&a)[3][2], const T (&b)[3][2], const T (&e)[3][2],
+                                           const T (&Ji)[9], const T lzy, const T mzy, const LinTabs<T, Q>& tb,
+                                           T (&S0)[3], T (&r1)[3][2], T (&r2)[3][2]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        S0[c] = T(0);
+        r1[c][0] = r1[c][1] = r2[c][0] = r2[c][1] = T(0);
+    }
+#pragma unroll
+    for (int qx = 0; qx < Q; ++qx) {
+        const T bx0 = tb.B0[qx], bx1 = tb.B1[qx];
+        T g[3][3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            g[c][0] = a[c][1] - a[c][0];
+            g[c][1] = bx0 * b[c][0] + bx1 * b[c][1];
+            g[c][2] = bx0 * e[c][0] + bx1 * e[c][1];
+        }
+        const T lam = lzy * tb.w[qx], mu = mzy * tb.w[qx];
+        T du[3][3];   // du[c][i] = d u_c / d x_i = sum_m Jinv[m][i] g[c][m]
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                du[c][i] = Ji[0 * 3 + i] * g[c][0] + Ji[1 * 3 + i] * g[c][1] + Ji[2 * 3 + i] * g[c][2];
+        const T div = du[0][0] + du[1][1] + du[2][2];
+        const T ld = lam * div, m2 = mu + mu;
+        T s[3][3];
+        s[0][0] = ld + m2 * du[0][0];
+        s[1][1] = ld + m2 * du[1][1];
+        s[2][2] = ld + m2 * du[2][2];
+        s[0][1] = s[1][0] = mu * (du[0][1] + du[1][0]);
+        s[0][2] = s[2][0] = mu * (du[0][2] + du[2][0]);
+        s[1][2] = s[2][1] = mu * (du[1][2] + du[2][1]);
+        // Q[c][m] = sum_i sigma[c][i] Jinv[m][i]; backward X
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T q0 = s[c][0] * Ji[0] + s[c][1] * Ji[1] + s[c][2] * Ji[2];
+            const T q1 = s[c][0] * Ji[3] + s[c][1] * Ji[4] + s[c][2] * Ji[5];
+            const T q2 = s[c][0] * Ji[6] + s[c][1] * Ji[7] + s[c][2] * Ji[8];
+            S0[c] += q0;
+            r1[c][0] += bx0 * q1;
+            r1[c][1] += bx1 * q1;
+            r2[c][0] += bx0 * q2;
+            r2[c][1] += bx1 * q2;
+        }
+    }
+}
+
+// Element contribution y_e = K_e x_e of one element with everything in registers,
+// added to ya (lower face iz = 0) and yb (upper face iz = 1); word k of a face is
+// (c, iy, ix) = (k >> 2, (k >> 1) & 1, k & 1).  Used in single precision, where
+// the lane's state fits two waves per SIMD.
+template <int Q, typename T>
+__device__ __forceinline__ void lin_element_reg(const T (&xa)[12], const T (&xb)[12], const T (&d)[12],
+                                                const LinTabs<T, Q>& tb, T (&ya)[12], T (&yb)[12]) {
     T Ji[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) Ji[k] = d[k];
     const T lw = d[9], mw = d[10];
-    T dz[3][2][2], U2[3][2][2];
+    T dz[12], U2[12];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int iy = 0; iy < 2; ++iy)
-#pragma unroll
-            for (int ix = 0; ix < 2; ++ix) {
-                dz[c][iy][ix] = xb[c][iy][ix] - xa[c][iy][ix];
-                U2[c][iy][ix] = T(0);
-            }
+    for (int k = 0; k < 12; ++k) {
+        dz[k] = xb[k] - xa[k];
+        U2[k] = T(0);
+    }
 #pragma unroll 1
     for (int qz = 0; qz < Q; ++qz) {
         const T bz0 = tb.B0[qz], bz1 = tb.B1[qz];
-        T xz[3][2][2], t0[3][2][2], t2[3][2][2];
+        T xz[12], t0[12], t2[12];
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int iy = 0; iy < 2; ++iy)
-#pragma unroll
-                for (int ix = 0; ix < 2; ++ix) {
-                    xz[c][iy][ix] = bz0 * xa[c][iy][ix] + bz1 * xb[c][iy][ix];
-                    t0[c][iy][ix] = T(0);
-                    t2[c][iy][ix] = T(0);
-                }
+        for (int k = 0; k < 12; ++k) {
+            xz[k] = bz0 * xa[k] + bz1 * xb[k];
+            t0[k] = t2[k] = T(0);
+        }
 #pragma unroll 1
         for (int qy = 0; qy < Q; ++qy) {
             const T by0 = tb.B0[qy], by1 = tb.B1[qy];
             const T wzy = tb.wzy[qz * Q + qy];
-            const T lzy = lw * wzy, mzy = mw * wzy;
-            // forward Y: a = B_y B_z x, b = G_y B_z x, e = B_y G_z x on the two x-columns ix
             T a[3][2], b[3][2], e[3][2];
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int ix = 0; ix < 2; ++ix) {
-                    a[c][ix] = by0 * xz[c][0][ix] + by1 * xz[c][1][ix];
-                    b[c][ix] = xz[c][1][ix] - xz[c][0][ix];
-                    e[c][ix] = by0 * dz[c][0][ix] + by1 * dz[c][1][ix];
+                    const T z0 = xz[c * 4 + ix], z1 = xz[c * 4 + 2 + ix];
+                    a[c][ix] = by0 * z0 + by1 * z1;
+                    b[c][ix] = z1 - z0;
+                    e[c][ix] = by0 * dz[c * 4 + ix] + by1 * dz[c * 4 + 2 + ix];
                 }
             T S0[3], r1[3][2], r2[3][2];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                S0[c] = T(0);
-                r1[c][0] = r1[c][1] = r2[c][0] = r2[c][1] = T(0);
-            }
-#pragma unroll
-            for (int qx = 0; qx < Q; ++qx) {
-                const T bx0 = tb.B0[qx], bx1 = tb.B1[qx];
-                // forward X: reference gradient g[c][m] at (qx, qy, qz)
-                T g[3][3];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    g[c][0] = a[c][1] - a[c][0];
-                    g[c][1] = bx0 * b[c][0] + bx1 * b[c][1];
-                    g[c][2] = bx0 * e[c][0] + bx1 * e[c][1];
-                }
-                const T lam = lzy * tb.w[qx], mu = mzy * tb.w[qx];
-                T du[3][3];   // du[c][i] = d u_c / d x_i = sum_m Jinv[m][i] g[c][m]
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-#pragma unroll
-                    for (int i = 0; i < 3; ++i)
-                        du[c][i] = Ji[0 * 3 + i] * g[c][0] + Ji[1 * 3 + i] * g[c][1] + Ji[2 * 3 + i] * g[c][2];
-                const T div = du[0][0] + du[1][1] + du[2][2];
-                const T ld = lam * div, m2 = mu + mu;
-                T s[3][3];
-                s[0][0] = ld + m2 * du[0][0];
-                s[1][1] = ld + m2 * du[1][1];
-                s[2][2] = ld + m2 * du[2][2];
-                s[0][1] = s[1][0] = mu * (du[0][1] + du[1][0]);
-                s[0][2] = s[2][0] = mu * (du[0][2] + du[2][0]);
-                s[1][2] = s[2][1] = mu * (du[1][2] + du[2][1]);
-                // Q[c][m] = sum_i sigma[c][i] Jinv[m][i]; backward X into (S0, r1, r2)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const T q0 = s[c][0] * Ji[0] + s[c][1] * Ji[1] + s[c][2] * Ji[2];
-                    const T q1 = s[c][0] * Ji[3] + s[c][1] * Ji[4] + s[c][2] * Ji[5];
-                    const T q2 = s[c][0] * Ji[6] + s[c][1] * Ji[7] + s[c][2] * Ji[8];
-                    S0[c] += q0;
-                    r1[c][0] += bx0 * q1;
-                    r1[c][1] += bx1 * q1;
-                    r2[c][0] += bx0 * q2;
-                    r2[c][1] += bx1 * q2;
-                }
-            }
+            lin_column<Q, T>(a, b, e, Ji, lw * wzy, mw * wzy, tb, S0, r1, r2);
             // backward Y: t0 += B_y (G_x channel) + G_y (channel 1), t2 += B_y (channel 2)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                t0[c][0][0] += -by0 * S0[c] - r1[c][0];
-                t0[c][0][1] += by0 * S0[c] - r1[c][1];
-                t0[c][1][0] += -by1 * S0[c] + r1[c][0];
-                t0[c][1][1] += by1 * S0[c] + r1[c][1];
+            for (int c = 0; c < 3; ++c)
 #pragma unroll
-                for (int ix = 0; ix < 2; ++ix) {
-                    t2[c][0][ix] += by0 * r2[c][ix];
-                    t2[c][1][ix] += by1 * r2[c][ix];
+                for (int iy = 0; iy < 2; ++iy) {
+                    const T by = iy ? by1 : by0;
+#pragma unroll
+                    for (int ix = 0; ix < 2; ++ix) {
+                        const int k = c * 4 + iy * 2 + ix;
+                        t0[k] += (ix ? by : -by) * S0[c] + (iy ? r1[c][ix] : -r1[c][ix]);
+                        t2[k] += by * r2[c][ix];
+                    }
                 }
-            }
         }
         // backward Z: B_z for channels 0 and 1; the G_z channel is summed over qz first
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int iy = 0; iy < 2; ++iy)
-#pragma unroll
-                for (int ix = 0; ix < 2; ++ix) {
-                    ya[c][iy][ix] += bz0 * t0[c][iy][ix];
-                    yb[c][iy][ix] += bz1 * t0[c][iy][ix];
-                    U2[c][iy][ix] += t2[c][iy][ix];
-                }
+        for (int k = 0; k < 12; ++k) {
+            ya[k] += bz0 * t0[k];
+            yb[k] += bz1 * t0[k];
+            U2[k] += t2[k];
+        }
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int iy = 0; iy < 2; ++iy)
-#pragma unroll
-            for (int ix = 0; ix < 2; ++ix) {
-                ya[c][iy][ix] -= U2[c][iy][ix];
-                yb[c][iy][ix] += U2[c][iy][ix];
-            }
+    for (int k = 0; k < 12; ++k) {
+        ya[k] -= U2[k];
+        yb[k] += U2[k];
+    }
 }
+
+// The same with the x faces read from the lane's LDS column (stride kLinLds) in
+// every (qz, qy) step and the backward Y/Z sweeps folded straight into the face
+// results: used in double precision, where this keeps the lane's state within
+// 256 VGPRs (two waves per SIMD instead of one).
+constexpr int kLinLds = 256;   // lanes per workgroup = LDS column stride
+
+// Compiler barrier: values staged in LDS are re-read after it instead of being
+// kept live in registers.
+__device__ __forceinline__ void lds_reload_point() { __asm__ volatile("" ::: "memory"); }
+
+template <int Q, typename T>
+__device__ __forceinline__ void lin_element_lds(const T* __restrict__ xa, const T* __restrict__ xb,
+                                                const T (&d)[12], const LinTabs<T, Q>& tb, T (&ya)[12],
+                                                T (&yb)[12]) {
+    constexpr int S = kLinLds;
+    T Ji[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Ji[k] = d[k];
+    const T lw = d[9], mw = d[10];
+#pragma unroll 1
+    for (int qz = 0; qz < Q; ++qz) {
+        const T bz0 = tb.B0[qz], bz1 = tb.B1[qz];
+#pragma unroll 1
+        for (int qy = 0; qy < Q; ++qy) {
+            lds_reload_point();
+            const T by0 = tb.B0[qy], by1 = tb.B1[qy];
+            const T wzy = tb.wzy[qz * Q + qy];
+            T a[3][2], b[3][2], e[3][2];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int ix = 0; ix < 2; ++ix) {
+                    const T a0 = xa[(c * 4 + ix) * S], a1 = xa[(c * 4 + 2 + ix) * S];
+                    const T b0 = xb[(c * 4 + ix) * S], b1 = xb[(c * 4 + 2 + ix) * S];
+                    const T z0 = bz0 * a0 + bz1 * b0, z1 = bz0 * a1 + bz1 * b1;
+                    a[c][ix] = by0 * z0 + by1 * z1;
+                    b[c][ix] = z1 - z0;
+                    e[c][ix] = by0 * (b0 - a0) + by1 * (b1 - a1);
+                }
+            T S0[3], r1[3][2], r2[3][2];
+            lin_column<Q, T>(a, b, e, Ji, lw * wzy, mw * wzy, tb, S0, r1, r2);
+            // backward Y and Z into the faces: t0 = B_y (G_x channel) + G_y (channel 1)
+            // takes B_z, t2 = B_y (channel 2) takes G_z = (-1, +1)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int iy = 0; iy < 2; ++iy) {
+                    const T by = iy ? by1 : by0;
+#pragma unroll
+                    for (int ix = 0; ix < 2; ++ix) {
+                        const int k = c * 4 + iy * 2 + ix;
+                        const T t0 = (ix ? by : -by) * S0[c] + (iy ? r1[c][ix] : -r1[c][ix]);
+                        const T t2 = by * r2[c][ix];
+                        ya[k] += bz0 * t0 - t2;
+                        yb[k] += bz1 * t0 + t2;
+                    }
+                }
+        }
+    }
+}
+
+template <typename T>
+constexpr bool kLinXInLds = sizeof(T) == 8;
 
 template <int Q, typename T>
 __global__ void __launch_bounds__(256)
 pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, const T* __restrict__ ed,
                     const LinTabs<T, Q> tb, const Geom g, const int add) {
     constexpr int TX = kLinTX, TY = kLinTY, TZ = kLinTZ;
-    static_assert(TX * TY == 64, "one tile per wavefront");
+    static_assert(TX * TY == 64 && kLinLds == 256, "one tile per wavefront, four per workgroup");
     const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + TZ - 1) / TZ;
     const int tile = xcd_block(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6);
     if (tile >= ntx * nty * ntz) return;   // the whole wavefront leaves together
@@ -210,7 +268,7 @@ pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ 
     const size_t NN = (size_t)g.Nn;
 
     // clamped corner nodes of the column's faces are read as 0 (constrained operator)
-    auto load_face = [&](int gz, T (&f)[3][2][2]) {
+    auto load_face = [&](int gz, T (&f)[12]) {
 #pragma unroll
         for (int iy = 0; iy < 2; ++iy)
 #pragma unroll
@@ -218,7 +276,7 @@ pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ 
                 const int node = (ex + ix) + g.Nx * ((ey + iy) + g.Ny * gz);
                 const bool use = valid && !(g.clamp && clamped_node(g.clamp, ex + ix, ey + iy, gz, g));
 #pragma unroll
-                for (int c = 0; c < 3; ++c) f[c][iy][ix] = use ? x[c * NN + node] : T(0);
+                for (int c = 0; c < 3; ++c) f[c * 4 + iy * 2 + ix] = use ? x[c * NN + node] : T(0);
             }
     };
     auto load_data = [&](int ez, T (&d)[12]) {
@@ -272,47 +330,81 @@ pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ 
             }
     };
 
-    T xa[3][2][2], xn[3][2][2], ya[3][2][2], dn[12];
-    load_face(ez0, xa);
-    load_face(ez0 + 1, xn);
-    load_data(ez0, dn);
+    T xn[12], dn[12], ya[12];
+    auto to_face = [](const T (&f)[12], T (&v)[3][2][2]) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+        for (int k = 0; k < 12; ++k) v[k >> 2][(k >> 1) & 1][k & 1] = f[k];
+    };
 #pragma unroll
-        for (int iy = 0; iy < 2; ++iy)
+    for (int k = 0; k < 12; ++k) ya[k] = T(0);
+    if constexpr (kLinXInLds<T>) {
+        // x faces in two alternating LDS buffers; the next element's data is loaded
+        // after the current element (two waves per SIMD hide the latency)
+        __shared__ T s_x[24 * kLinLds];
+        T* const col = s_x + threadIdx.x;
+        auto store_face = [&](int buf, const T (&f)[12]) {
 #pragma unroll
-            for (int ix = 0; ix < 2; ++ix) ya[c][iy][ix] = T(0);
+            for (int k = 0; k < 12; ++k) col[(12 * buf + k) * kLinLds] = f[k];
+        };
+        load_face(ez0, xn);
+        store_face(0, xn);
+        load_face(ez0 + 1, xn);
+        load_data(ez0, dn);
+        int fa = 0;
 #pragma unroll 1
-    for (int ez = ez0; ez < ez1; ++ez) {
-        T xb[3][2][2], d[12], yb[3][2][2];
+        for (int ez = ez0; ez < ez1; ++ez) {
+            T d[12], yb[12];
+            store_face(1 - fa, xn);
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+            for (int k = 0; k < 12; ++k) {
+                d[k] = dn[k];
+                yb[k] = T(0);
+            }
+            lin_element_lds<Q, T>(col + 12 * fa * kLinLds, col + 12 * (1 - fa) * kLinLds, d, tb, ya, yb);
+            if (ez + 1 < ez1) {
+                load_face(ez + 2, xn);
+                load_data(ez + 1, dn);
+            }
+            T v[3][2][2];
+            to_face(ya, v);
+            emit_layer(v, ez);
 #pragma unroll
-            for (int iy = 0; iy < 2; ++iy)
-#pragma unroll
-                for (int ix = 0; ix < 2; ++ix) {
-                    xb[c][iy][ix] = xn[c][iy][ix];
-                    yb[c][iy][ix] = T(0);
-                }
-#pragma unroll
-        for (int k = 0; k < 12; ++k) d[k] = dn[k];
-        if (ez + 1 < ez1) {   // prefetch the next element of the column
-            load_face(ez + 2, xn);
-            load_data(ez + 1, dn);
+            for (int k = 0; k < 12; ++k) ya[k] = yb[k];
+            fa ^= 1;
         }
-        lin_element<Q, T>(xa, xb, d, tb, ya, yb);
-        emit_layer(ya, ez);
+    } else {
+        // everything in registers; the next element's data is prefetched
+        T xa[12];
+        load_face(ez0, xa);
+        load_face(ez0 + 1, xn);
+        load_data(ez0, dn);
+#pragma unroll 1
+        for (int ez = ez0; ez < ez1; ++ez) {
+            T xb[12], d[12], yb[12];
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+            for (int k = 0; k < 12; ++k) {
+                xb[k] = xn[k];
+                d[k] = dn[k];
+                yb[k] = T(0);
+            }
+            if (ez + 1 < ez1) {
+                load_face(ez + 2, xn);
+                load_data(ez + 1, dn);
+            }
+            lin_element_reg<Q, T>(xa, xb, d, tb, ya, yb);
+            T v[3][2][2];
+            to_face(ya, v);
+            emit_layer(v, ez);
 #pragma unroll
-            for (int iy = 0; iy < 2; ++iy)
-#pragma unroll
-                for (int ix = 0; ix < 2; ++ix) {
-                    xa[c][iy][ix] = xb[c][iy][ix];
-                    ya[c][iy][ix] = yb[c][iy][ix];
-                }
+            for (int k = 0; k < 12; ++k) {
+                xa[k] = xb[k];
+                ya[k] = yb[k];
+            }
+        }
     }
-    emit_layer(ya, ez1);
+    T v[3][2][2];
+    to_face(ya, v);
+    emit_layer(v, ez1);
 }
 
 // For every node on a tile boundary: sum the partial sums of the tiles touching it
