@@ -197,15 +197,61 @@ struct Skel {
     }
 };
 
+// LDS layout of one element: Ua[ch][iz][iy][qx] (X-pass output, two channels;
+// reused for the backward Y output) and Ra[ch][iz][qy][qx] (Y-pass output, three
+// channels; reused for the backward Z output), qx contiguous.  Strides in words.
+struct LdsStrides {
+    int UY, UZ, UC, UT;   // Ua: iy, iz, channel, element
+    int RY, RZ, RC, ST;   // Ra: qy, iz, channel, element
+};
+
+// Padded strides for q = p + 2, chosen to minimise bank conflicts of the four access
+// patterns (X lines, Y lines on Ua, Y lines on Ra, Z columns): each candidate was
+// scored by the largest number of lanes that share a bank within every group of 16
+// lanes (8-byte words) or 32 lanes (4-byte words), summed over the kernel's LDS
+// instructions, with the element footprint capped at 1.25x the unpadded one.
+// Other (p, q) use a plain layout with odd row strides.
+constexpr LdsStrides lds_strides(int P, int Q, int word) {
+    if (Q == P + 2 && word == 8) {
+        switch (P) {
+            case 2: return {5, 20, 54, 108, 4, 20, 56, 172};
+            case 3: return {5, 20, 80, 160, 5, 26, 105, 313};
+            case 4: return {7, 35, 174, 351, 6, 38, 188, 574};
+            case 5: return {7, 42, 256, 508, 7, 55, 324, 986};
+            case 6: return {9, 63, 440, 880, 8, 72, 496, 1488};
+            case 7: return {10, 89, 702, 1416, 9, 89, 704, 2120};
+            case 8: return {13, 117, 1050, 2100, 10, 106, 948, 2844};
+        }
+    }
+    if (Q == P + 2 && word == 4) {
+        switch (P) {
+            case 2: return {4, 12, 37, 81, 4, 20, 60, 176};
+            case 3: return {5, 20, 80, 176, 5, 26, 103, 313};
+            case 4: return {7, 38, 201, 414, 6, 38, 188, 574};
+            case 5: return {7, 42, 272, 540, 7, 52, 309, 945};
+            case 6: return {9, 72, 494, 988, 8, 72, 496, 1488};
+            case 7: return {9, 72, 576, 1152, 9, 85, 676, 2033};
+            case 8: return {13, 117, 1050, 2100, 10, 106, 948, 2844};
+        }
+    }
+    const int D = P + 1, QP = Q | 1;
+    return {QP, D * QP, D * D * QP, 2 * D * D * QP, Q, Q * Q, D * Q * Q, 3 * D * Q * Q};
+}
+
 // Elements per workgroup: fill 64-lane waves with the E*Q*Q quadrature columns while
 // keeping the workgroup's LDS at or below 64 KiB.
 template <int P, int Q, typename T>
 struct ApplyCfg {
     static constexpr int D = P + 1;
     static constexpr int QQ = Q * Q;
-    static constexpr int QP = Q | 1;                 // padded (odd) row stride, in words
-    static constexpr int UT = 2 * D * D * QP;        // X-pass output (two channels) | backward Y output
-    static constexpr int ST = 3 * D * QQ;            // Y-pass output (three channels) | backward Z output
+    static constexpr LdsStrides L = lds_strides(P, Q, (int)sizeof(T));
+    static constexpr int UT = L.UT, ST = L.ST;
+    static_assert(L.UY >= Q && L.UZ >= (D - 1) * L.UY + Q && L.UC >= (D - 1) * (L.UZ + L.UY) + Q &&
+                      L.UT >= L.UC + (D - 1) * (L.UZ + L.UY) + Q,
+                  "Ua strides overlap");
+    static_assert(L.RY >= Q && L.RZ >= (Q - 1) * L.RY + Q && L.RC >= (D - 1) * L.RZ + (Q - 1) * L.RY + Q &&
+                      L.ST >= 2 * L.RC + (D - 1) * L.RZ + (Q - 1) * L.RY + Q,
+                  "Ra strides overlap");
     static constexpr int LDS_ELEM = ST + UT + kEdStride;
     static constexpr int pickE() {
         int bestE = 1;
@@ -238,7 +284,8 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
     using C = ApplyCfg<P, Q, T>;
     using SK = Skel<P + 1>;
     constexpr int D = P + 1, E = C::E, NT = C::NT, QQ = Q * Q;
-    constexpr int QP = C::QP, UT = C::UT, ST = C::ST;
+    constexpr int UT = C::UT, ST = C::ST;
+    constexpr int UY = C::L.UY, UZ = C::L.UZ, UC = C::L.UC, RY = C::L.RY, RZ = C::L.RZ, RC = C::L.RC;
     __shared__ T Ra[E * ST];          // Y-pass output | backward Z output
     __shared__ T Ua[E * UT];          // X-pass output | backward Y output
     __shared__ T Es[E * kEdStride];   // per-element PA data of the block
@@ -320,11 +367,11 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
                 T u[Q], v[Q];
                 eo_contract<1, false>(xr[j], u, tab.Bf);
                 eo_contract<-1, false>(xr[j], v, tab.Gf);
-                T* uo = Ua + el * UT + r * QP;
+                T* uo = Ua + el * UT + (r / D) * UZ + (r % D) * UY;
 #pragma unroll
                 for (int k = 0; k < Q; ++k) {
                     uo[k] = u[k];
-                    uo[D * D * QP + k] = v[k];
+                    uo[UC + k] = v[k];
                 }
             }
         }
@@ -334,31 +381,31 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
         for (int w = tid; w < E * D * Q; w += NT) {
             const int el = w / (D * Q), r = w % (D * Q);
             const int iz = r / Q, qx = r % Q;
-            const T* ui = Ua + el * UT + iz * D * QP + qx;
+            const T* ui = Ua + el * UT + iz * UZ + qx;
             T uv[D], vv[D], s0[Q], s1[Q], s2[Q];
 #pragma unroll
-            for (int i = 0; i < D; ++i) { uv[i] = ui[i * QP]; vv[i] = ui[D * D * QP + i * QP]; }
+            for (int i = 0; i < D; ++i) { uv[i] = ui[i * UY]; vv[i] = ui[UC + i * UY]; }
             eo_contract<1, false>(vv, s0, tab.Bf);
             eo_contract<-1, false>(uv, s1, tab.Gf);
             eo_contract<1, false>(uv, s2, tab.Bf);
-            T* so = Ra + el * ST + iz * QQ + qx;
+            T* so = Ra + el * ST + iz * RZ + qx;
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
-                so[k * Q] = s0[k];
-                so[D * QQ + k * Q] = s1[k];
-                so[2 * D * QQ + k * Q] = s2[k];
+                so[k * RY] = s0[k];
+                so[RC + k * RY] = s1[k];
+                so[2 * RC + k * RY] = s2[k];
             }
         }
         __syncthreads();
         // ---- forward Z: the thread's own (qx,qy) column
         if (has_col) {
-            const T* si = Ra + cel * ST + cq;
+            const T* si = Ra + cel * ST + cqy * RY + cqx;
             T i0[D], i1[D], i2[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                i0[i] = si[i * QQ];
-                i1[i] = si[D * QQ + i * QQ];
-                i2[i] = si[2 * D * QQ + i * QQ];
+                i0[i] = si[i * RZ];
+                i1[i] = si[RC + i * RZ];
+                i2[i] = si[2 * RC + i * RZ];
             }
             eo_contract<1, false>(i0, gq[c][0], tab.Bf);
             eo_contract<1, false>(i1, gq[c][1], tab.Bf);
@@ -413,12 +460,12 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
             eo_contract<1, false>(gq[c][0], t0, tab.Bt);
             eo_contract<1, false>(gq[c][1], t1, tab.Bt);
             eo_contract<-1, false>(gq[c][2], t2, tab.Gt);
-            T* so = Ra + cel * ST + cq;
+            T* so = Ra + cel * ST + cqy * RY + cqx;
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                so[i * QQ] = t0[i];
-                so[D * QQ + i * QQ] = t1[i];
-                so[2 * D * QQ + i * QQ] = t2[i];
+                so[i * RZ] = t0[i];
+                so[RC + i * RZ] = t1[i];
+                so[2 * RC + i * RZ] = t2[i];
             }
         }
         __syncthreads();
@@ -426,21 +473,21 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
         for (int w = tid; w < E * D * Q; w += NT) {
             const int el = w / (D * Q), r = w % (D * Q);
             const int iz = r / Q, qx = r % Q;
-            const T* ti = Ra + el * ST + iz * QQ + qx;
+            const T* ti = Ra + el * ST + iz * RZ + qx;
             T a0[Q], a1[Q], a2[Q], r0[D], r12[D];
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
-                a0[k] = ti[k * Q];
-                a1[k] = ti[D * QQ + k * Q];
-                a2[k] = ti[2 * D * QQ + k * Q];
+                a0[k] = ti[k * RY];
+                a1[k] = ti[RC + k * RY];
+                a2[k] = ti[2 * RC + k * RY];
             }
             eo_contract<1, false>(a0, r0, tab.Bt);
             eo_contract2<-1, 1>(a1, tab.Gt, a2, tab.Bt, r12);
-            T* ro = Ua + el * UT + iz * D * QP + qx;
+            T* ro = Ua + el * UT + iz * UZ + qx;
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                ro[i * QP] = r0[i];
-                ro[D * D * QP + i * QP] = r12[i];
+                ro[i * UY] = r0[i];
+                ro[UC + i * UY] = r12[i];
             }
         }
         __syncthreads();
@@ -452,10 +499,10 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
             if (l < NL && ln_node[j] >= 0) {
                 const int el = l / (D * D), r = l % (D * D);
                 const int iz = r / D, iy = r % D;
-                const T* ri = Ua + el * UT + r * QP;
+                const T* ri = Ua + el * UT + iz * UZ + iy * UY;
                 T a0[Q], a1[Q], yo[D];
 #pragma unroll
-                for (int k = 0; k < Q; ++k) { a0[k] = ri[k]; a1[k] = ri[D * D * QP + k]; }
+                for (int k = 0; k < Q; ++k) { a0[k] = ri[k]; a1[k] = ri[UC + k]; }
                 eo_contract2<-1, 1>(a0, tab.Gt, a1, tab.Bt, yo);
 #pragma unroll
                 for (int ix = 0; ix < D; ++ix) {
