@@ -188,10 +188,11 @@ struct Skel {
     __device__ __forceinline__ static bool interior(int ix, int iy, int iz) {
         return ix > 0 && ix < P && iy > 0 && iy < P && iz > 0 && iz < P;
     }
-    // Buffer layout: element-major ([e][c][s]) from p = 3 on, so that consecutive nodes
-    // of one element face are contiguous; node-major ([c][s][e]) at p <= 2, where
-    // consecutive nodes belong to consecutive elements.
-    static constexpr bool ELEM_MAJOR = D >= 4;
+    // Buffer layout: node-major ([c][s][e]) up to p = 5, so that the skeleton kernel's
+    // reads of one slot for consecutive elements are contiguous; element-major
+    // ([e][c][s]) from p = 6 on, where an element's slots are many and its face rows
+    // long enough to keep the apply kernel's writes contiguous (measured crossover).
+    static constexpr bool ELEM_MAJOR = D >= 7;
     __device__ __forceinline__ static size_t offset(int e, int c, int s, int NE) {
         return ELEM_MAJOR ? ((size_t)e * 3 + c) * S + s : ((size_t)c * S + s) * NE + e;
     }
