@@ -60,6 +60,8 @@ extern "C" {
 /* ---- solver modes / stopping tests ----------------------------------------- */
 #define PA_SOLVE_F64 0        /* FP64 PCG with an FP64 V-cycle                                */
 #define PA_SOLVE_F32_IR 1     /* FP64 iterative refinement around an FP32 PCG + FP32 V-cycle  */
+#define PA_SOLVE_F32_PREC 2   /* FP64 PCG (FP64 apply, residual, dots) preconditioned by the
+                                 FP32 V-cycle (FP32 applies, smoothers, transfers)              */
 #define PA_STOP_PREC 0        /* sqrt(r.Br / r0.Br0) <= rtol (preconditioned norm)            */
 #define PA_STOP_TRUE 1        /* |b - A x|_2 / |b|_2 <= rtol (true residual)                  */
 
@@ -77,7 +79,7 @@ typedef struct pa_gmg pa_gmg_t;
 typedef struct pa_solve pa_solve_t;
 
 typedef struct pa_solve_opts_t {
-    int mode;                 /* PA_SOLVE_F64 or PA_SOLVE_F32_IR                               */
+    int mode;                 /* PA_SOLVE_F64, PA_SOLVE_F32_IR or PA_SOLVE_F32_PREC            */
     int stop;                 /* PA_STOP_PREC or PA_STOP_TRUE                                  */
     int p_levels;             /* number of p-coarsenings p -> p/2 -> ... (-1: down to p = 1)   */
     int h_levels;             /* number of h-coarsenings at p = 1 (-1: automatic)              */
@@ -131,7 +133,9 @@ int pa_elast_set_stream(pa_op_t* op, void* hip_stream);
 int pa_elast_ndofs(const pa_op_t* op, int64_t* n);
 /* Device bytes an operator (with_solver = 0) or an operator plus a default GMG
  * solver hierarchy and its work vectors (with_solver = 1) needs; used for
- * admission by HBM budget.  Returns a negative error code on bad input. */
+ * admission by HBM budget.  with_solver models PA_SOLVE_F64 for dtype PA_F64
+ * (an upper bound for PA_SOLVE_F32_PREC, whose levels are FP32) and
+ * PA_SOLVE_F32_IR for dtype PA_F32.  Returns a negative error code on bad input. */
 int64_t pa_bytes_required(const pa_mesh_t* m, int p, int dtype, int with_solver);
 
 /* y = A x (async).  The fused kernel gathers each element's dofs (the

@@ -13,11 +13,11 @@ from typing import Optional
 import numpy as np
 
 from . import capi
-from .capi import (PA_ADD, PA_F32, PA_F64, PA_SOLVE_F32_IR, PA_SOLVE_F64, PA_STOP_PREC, PA_STOP_TRUE,
+from .capi import (PA_ADD, PA_F32, PA_F64, PA_SOLVE_F32_IR, PA_SOLVE_F32_PREC, PA_SOLVE_F64, PA_STOP_PREC, PA_STOP_TRUE,
                    PA_UNCONSTRAINED, PaError)
 
 __all__ = ["Operator", "Hierarchy", "mesh_struct", "capi", "PA_F64", "PA_F32", "PA_UNCONSTRAINED", "PA_ADD",
-           "PA_SOLVE_F64", "PA_SOLVE_F32_IR", "PA_STOP_PREC", "PA_STOP_TRUE", "PaError", "solve_opts"]
+           "PA_SOLVE_F64", "PA_SOLVE_F32_IR", "PA_SOLVE_F32_PREC", "PA_STOP_PREC", "PA_STOP_TRUE", "PaError", "solve_opts"]
 
 
 def _torch():

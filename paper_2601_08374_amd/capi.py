@@ -27,6 +27,7 @@ PA_UNCONSTRAINED = 1
 PA_ADD = 2
 PA_SOLVE_F64 = 0
 PA_SOLVE_F32_IR = 1
+PA_SOLVE_F32_PREC = 2
 PA_STOP_PREC = 0
 PA_STOP_TRUE = 1
 

@@ -147,7 +147,8 @@ struct pa_gmg {
     pa_op* fine64 = nullptr;
     bool own_fine64 = false;
     pa_solve_opts_t opts;
-    int vdtype = PA_F64;
+    int vdtype = PA_F64;     // precision of the levels (V-cycle)
+    int mode = PA_SOLVE_F64;
     std::vector<pa::Level> L;
     int Nc = 0;
     void* cinv = nullptr;
@@ -156,6 +157,7 @@ struct pa_gmg {
     double* scal = nullptr;
     double* hscal = nullptr;
     void *pr = nullptr, *pz = nullptr, *pp = nullptr, *pAp = nullptr, *pd = nullptr;
+    void* pz32 = nullptr;    // PA_SOLVE_F32_PREC: FP32 V-cycle output
     double* r64 = nullptr;
     double* t64 = nullptr;
     hipEvent_t ev = nullptr;
@@ -357,8 +359,8 @@ void destroy_gmg(pa_gmg* G) {
     if (G->stream) (void)hipStreamSynchronize(G->stream);
     for (auto& v : G->L) free_level(v);
     if (G->own_fine64 && G->fine64) pa_elast_destroy(G->fine64);
-    for (void* p : {G->cinv, (void*)G->part, (void*)G->scal, G->pr, G->pz, G->pp, G->pAp, G->pd, (void*)G->r64,
-                    (void*)G->t64})
+    for (void* p : {G->cinv, (void*)G->part, (void*)G->scal, G->pr, G->pz, G->pp, G->pAp, G->pd, G->pz32,
+                    (void*)G->r64, (void*)G->t64})
         if (p) (void)hipFree(p);
     if (G->hscal) (void)hipHostFree(G->hscal);
     if (G->ev) (void)hipEventDestroy(G->ev);
@@ -368,7 +370,8 @@ void destroy_gmg(pa_gmg* G) {
 int setup_gmg(pa_op* op, const pa_solve_opts_t* o, pa_gmg** out) {
     pa_solve_opts_t opts;
     if (o) opts = *o; else pa_solve_opts_default(&opts);
-    if (opts.mode != PA_SOLVE_F64 && opts.mode != PA_SOLVE_F32_IR) return fail(PA_EINVAL, "mode %d", opts.mode);
+    if (opts.mode != PA_SOLVE_F64 && opts.mode != PA_SOLVE_F32_IR && opts.mode != PA_SOLVE_F32_PREC)
+        return fail(PA_EINVAL, "mode %d", opts.mode);
     if (opts.stop != PA_STOP_PREC && opts.stop != PA_STOP_TRUE) return fail(PA_EINVAL, "stop %d", opts.stop);
     if (opts.cheb_degree < 1 || opts.cheb_degree > 64) return fail(PA_EINVAL, "cheb_degree %d", opts.cheb_degree);
     if (opts.power_iters < 1) return fail(PA_EINVAL, "power_iters %d", opts.power_iters);
@@ -381,7 +384,8 @@ int setup_gmg(pa_op* op, const pa_solve_opts_t* o, pa_gmg** out) {
     G->user = op;
     G->opts = opts;
     G->stream = op->stream;
-    G->vdtype = opts.mode == PA_SOLVE_F32_IR ? PA_F32 : PA_F64;
+    G->mode = opts.mode;
+    G->vdtype = opts.mode == PA_SOLVE_F64 ? PA_F64 : PA_F32;
     int rc = PA_OK;
     do {
         const std::vector<LevelPlan> plan = plan_levels(op->mesh, op->p, opts);
@@ -443,6 +447,7 @@ int setup_gmg(pa_op* op, const pa_solve_opts_t* o, pa_gmg** out) {
             break;
         }
         PA_HIP(hipMemsetAsync(G->scal, 0, S_COUNT * sizeof(double), G->stream));
+        if ((rc = launch_fill(G->scal + S_ONE, PA_F64, 1, 1.0, G->stream))) break;
         for (size_t l = 0; l + 1 < plan.size() && !rc; ++l) rc = build_transfer(G, (int)l, plan[l], plan[l + 1]);
         if (rc) break;
         // smoothers: diagonal, lambda_max
@@ -488,12 +493,16 @@ int setup_gmg(pa_op* op, const pa_solve_opts_t* o, pa_gmg** out) {
             G->cinv = A;
             if (rc) break;
         }
-        // PCG work vectors (inner precision) and the FP64 outer operator
+        // PCG work vectors (PCG precision) and the FP64 outer operator
         const int64_t N0 = G->L[0].N;
-        if ((rc = alloc_vec(&G->pr, N0, G->vdtype)) || (rc = alloc_vec(&G->pz, N0, G->vdtype)) ||
-            (rc = alloc_vec(&G->pp, N0, G->vdtype)) || (rc = alloc_vec(&G->pAp, N0, G->vdtype)))
+        const int pdt = G->mode == PA_SOLVE_F32_IR ? PA_F32 : PA_F64;
+        if ((rc = alloc_vec(&G->pr, N0, pdt)) || (rc = alloc_vec(&G->pz, N0, pdt)) ||
+            (rc = alloc_vec(&G->pp, N0, pdt)) || (rc = alloc_vec(&G->pAp, N0, pdt)))
             break;
-        if (G->vdtype == PA_F32) {
+        if (G->mode == PA_SOLVE_F32_PREC) {
+            if ((rc = alloc_vec(&G->pd, N0, PA_F32)) || (rc = alloc_vec(&G->pz32, N0, PA_F32))) break;
+        }
+        if (G->mode == PA_SOLVE_F32_IR) {
             if ((rc = alloc_vec(&G->pd, N0, PA_F32)) || (rc = alloc_vec((void**)&G->r64, N0, PA_F64)) ||
                 (rc = alloc_vec((void**)&G->t64, N0, PA_F64)))
                 break;
@@ -537,8 +546,19 @@ struct InnerCtx {
 
 InnerCtx inner_ctx(pa_solve* S) {
     pa_gmg* G = S->G;
-    if (G->vdtype == PA_F32) return {G->L[0].op, G->pd, PA_F32, G->L[0].N};
+    if (G->mode == PA_SOLVE_F32_IR) return {G->L[0].op, G->pd, PA_F32, G->L[0].N};
     return {G->fine64, S->x, PA_F64, G->L[0].N};
+}
+
+// Preconditioner z = B r of the PCG: the V-cycle in the levels' precision; in
+// PA_SOLVE_F32_PREC mode r and z are FP64 and the V-cycle runs in FP32 between two casts.
+int precondition(pa_gmg* G, const void* r, void* z) {
+    if (G->mode != PA_SOLVE_F32_PREC) return vcycle(G, 0, r, z);
+    const int64_t N = G->L[0].N;
+    int rc;
+    if ((rc = launch_cast_scale(G->pd, PA_F32, r, PA_F64, G->scal, S_ONE, 0, N, G->stream))) return rc;
+    if ((rc = vcycle(G, 0, G->pd, G->pz32))) return rc;
+    return launch_cast_scale(z, PA_F64, G->pz32, PA_F32, G->scal, S_ONE, 0, N, G->stream);
 }
 
 // Start the inner PCG on A x = b_in where r already holds b_in - A x: z = B r, p = z, rz0.
@@ -546,7 +566,7 @@ int inner_begin(pa_solve* S, double rtol, int stop) {
     pa_gmg* G = S->G;
     InnerCtx c = inner_ctx(S);
     int rc;
-    if ((rc = vcycle(G, 0, G->pr, G->pz))) return rc;
+    if ((rc = precondition(G, G->pr, G->pz))) return rc;
     if ((rc = launch_copy(G->pp, G->pz, c.dt, c.N, G->stream))) return rc;
     if ((rc = launch_dot(G->pr, G->pz, G->pr, c.dt, c.N, G->part, G->stream))) return rc;
     S->inner_iters = 0;
@@ -562,7 +582,7 @@ int inner_iteration(pa_solve* S) {
     if ((rc = launch_dot(G->pp, G->pAp, nullptr, c.dt, c.N, G->part, s))) return rc;
     if ((rc = launch_dot_final(G->part, G->scal, FIN_ALPHA, 0, s))) return rc;
     if ((rc = launch_pcg_xr(c.x, G->pr, G->pp, G->pAp, G->scal, c.dt, c.N, s))) return rc;
-    if ((rc = vcycle(G, 0, G->pr, G->pz))) return rc;
+    if ((rc = precondition(G, G->pr, G->pz))) return rc;
     if ((rc = launch_dot(G->pr, G->pz, G->pr, c.dt, c.N, G->part, s))) return rc;
     if ((rc = launch_dot_final(G->part, G->scal, FIN_BETA, 0, s))) return rc;
     if ((rc = launch_pcg_p(G->pp, G->pz, G->scal, c.dt, c.N, s))) return rc;
@@ -583,7 +603,7 @@ int outer_residual(pa_solve* S, double* r, double* tmp) {
 
 int enqueue_inner_batch(pa_solve* S, int n) {
     const pa_solve_opts_t& o = S->G->opts;
-    const bool ir = S->G->vdtype == PA_F32;
+    const bool ir = S->G->mode == PA_SOLVE_F32_IR;
     int rc;
     for (int i = 0; i < n; ++i) {
         if (ir ? S->inner_iters >= o.inner_max_iter : S->total_iters >= o.max_iter) break;
@@ -604,7 +624,7 @@ int solve_begin(pa_gmg* G, const double* b, double* x, double rtol, pa_solve* S)
     if ((rc = launch_dot(b, b, nullptr, PA_F64, G->fine64->N, G->part, s))) return rc;
     if ((rc = launch_dot_final(G->part, G->scal, FIN_STORE, S_NB, s))) return rc;
     if ((rc = launch_dot_final(G->part, G->scal, FIN_STORE, S_BB, s))) return rc;
-    if (G->vdtype == PA_F64) {
+    if (G->mode != PA_SOLVE_F32_IR) {
         // r = b - A x
         if ((rc = apply_op(G->fine64, x, G->pAp, 0))) return rc;
         if ((rc = launch_residual(G->pr, b, G->pAp, PA_F64, G->fine64->N, s))) return rc;
@@ -624,7 +644,7 @@ int solve_advance(pa_solve* S, int batch, bool may_enqueue) {
     const pa_solve_opts_t& o = G->opts;
     int rc;
     if (S->phase == 2) return PA_OK;
-    if (G->vdtype == PA_F64) {
+    if (G->mode != PA_SOLVE_F32_IR) {
         if (S->phase == 1) {
             // true-residual check after the recursive residual met the test: the recursion
             // drifts from b - A x, so restart from the current x when the true one is too big
@@ -691,8 +711,9 @@ int solve_end(pa_solve* S, pa_solve_info_t* info) {
     const double t_solve = now_s() - S->t0;
     if (info) {
         // true FP64 residual of the returned x
-        double* r = G->vdtype == PA_F32 ? G->r64 : (double*)G->pr;
-        double* tmp = G->vdtype == PA_F32 ? G->t64 : (double*)G->pAp;
+        const bool ir = G->mode == PA_SOLVE_F32_IR;
+        double* r = ir ? G->r64 : (double*)G->pr;
+        double* tmp = ir ? G->t64 : (double*)G->pAp;
         int rc = outer_residual(S, r, tmp);
         if (rc) return rc;
         if ((rc = sync_scalars(G))) return rc;

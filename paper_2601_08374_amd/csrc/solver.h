@@ -18,6 +18,7 @@ enum {
     S_T0 = 16, S_T1 = 17,      // scratch pair for FIN_STORE
     S_NR = 20, S_NR1 = 21,     // |r|^2 of the refinement residual
     S_NB = 22, S_NB1 = 23,     // |b|^2
+    S_ONE = 24,                // constant 1.0 (plain casts through launch_cast_scale)
     S_COUNT = 32
 };
 

@@ -222,12 +222,12 @@ class KeepingExecutor(GpuExecutor):
 def bench_stream(num: int = 64, seed: int = 5, slots: int = 8, budget_gb: float = 64.0, n_hi: int = 32,
                  rate: Optional[float] = None):
     """Serving benchmark: closed-loop capacity on a sample, then Poisson arrivals at 0.8x it,
-    for FP32+refinement and for plain FP64."""
+    for FP32+refinement, FP64 PCG with the FP32 V-cycle, and plain FP64."""
     import synthetic as syn
     import paper_2601_08374_amd as pa
     out = {"requests": num, "slots": slots, "budget_gb": budget_gb, "rtol": 1e-8, "n_range": [4, n_hi],
            "p_choices": [2, 4, 6, 8]}
-    for mode, name in ((pa.PA_SOLVE_F32_IR, "f32_ir"), (pa.PA_SOLVE_F64, "f64")):
+    for mode, name in ((pa.PA_SOLVE_F32_IR, "f32_ir"), (pa.PA_SOLVE_F32_PREC, "f32_prec"), (pa.PA_SOLVE_F64, "f64")):
         ex = GpuExecutor(mode=mode, slots=slots)
         reqs = syn.serving_stream(num, rate=1.0, seed=seed, n_hi=n_hi)
         sched = Scheduler(ex, slots=slots, budget_bytes=int(budget_gb * (1 << 30)))

@@ -11,7 +11,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_alone_equals_mix(mode):
     from paper_2601_08374_amd.serve import KeepingExecutor, Scheduler, summarize
     reqs = syn.serving_stream(10, rate=2000.0, seed=3, n_lo=4, n_hi=9, ps=(2, 4))

@@ -248,7 +248,7 @@ def test_config1_pcg_vs_direct():
 
 
 @pytest.mark.parametrize("p", [4, 8])
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_small_cantilever_vs_direct(p, mode):
     pa = _pa()
     nx = 8 if p == 4 else 4
@@ -319,7 +319,7 @@ def _full_cantilever(p, mode):
     return mesh, op, b, x, info, rc, lam, mu
 
 
-@pytest.mark.parametrize("p,mode", [(8, 0), (8, 1), (4, 1)])
+@pytest.mark.parametrize("p,mode", [(8, 0), (8, 1), (4, 1), (8, 2)])
 def test_full_size_cantilever_oracle_residual(p, mode):
     """The 80x8x8 cantilever (8.1M dofs at p=8): the oracle's own FP64 apply gives the
     true residual of the GPU solution; tip deflection vs beam theory as a sanity check."""
@@ -340,3 +340,15 @@ def test_full_size_cantilever_oracle_residual(p, mode):
     assert 0.95 * 2048 < defl < 1.05 * 2048 * 1.012
     print(f"p={p} mode={mode}: iters {info.iters} outer {info.outer_iters} res {res:.2e} "
           f"t_setup {info.t_setup:.2f}s t_solve {info.t_solve:.2f}s tip {defl:.2f}")
+
+
+def test_solver_mode_validation():
+    pa = _pa()
+    mesh = syn.BoxMesh(n=(2, 2, 2), clamped_faces=1)
+    op = pa.Operator(mesh, 2, np.full(8, 1.0), np.full(8, 1.0))
+    with pytest.raises(pa.PaError) as e:
+        op.hierarchy(mode=3)
+    assert e.value.code == pa.capi.PA_EINVAL
+    H = op.hierarchy(mode=pa.PA_SOLVE_F32_PREC)
+    assert H.num_levels >= 2
+    H.close()
