@@ -10,7 +10,7 @@
 // derivative contraction is a difference.
 //
 // A wavefront is a tile of kLinTX x kLinTY element columns (lane = column);
-// each lane walks kLinTZ elements up its column, carrying the upper face of
+// each lane walks a chunk of lin_chunk() elements up its column, carrying the upper face of
 // one element (x values and partial results) in registers into the next, and
 // prefetching the next element's x face and PA data while it computes.  After
 // each element the finished node layer is summed across lanes with shuffles
@@ -53,9 +53,10 @@ __device__ __forceinline__ void load_ed12(const float* p, float (&d)[12]) {
     }
 }
 
-// Slot of node (lx, ly, lz) of tile t (local node coordinates in the tile's node box).
-__device__ __forceinline__ size_t lin_slot(int t, int c, int lz, int ly, int lx) {
-    return (((size_t)t * 3 + c) * (kLinTZ + 1) + lz) * ((kLinTY + 1) * (kLinTX + 1)) + ly * (kLinTX + 1) + lx;
+// Slot of node (lx, ly, lz) of tile t (local node coordinates in the tile's node box;
+// tz = elements per tile along z).
+__device__ __forceinline__ size_t lin_slot(int t, int c, int lz, int ly, int lx, int tz) {
+    return (((size_t)t * 3 + c) * (tz + 1) + lz) * ((kLinTY + 1) * (kLinTX + 1)) + ly * (kLinTX + 1) + lx;
 }
 
 // One (qy, qz) column of quadrature points: forward X to the reference gradient
@@ -250,8 +251,8 @@ constexpr bool kLinXInLds = sizeof(T) == 8;
 template <int Q, typename T>
 __global__ void __launch_bounds__(256)
 pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, const T* __restrict__ ed,
-                    const LinTabs<T, Q> tb, const Geom g, const int add) {
-    constexpr int TX = kLinTX, TY = kLinTY, TZ = kLinTZ;
+                    const LinTabs<T, Q> tb, const Geom g, const int TZ, const int add) {
+    constexpr int TX = kLinTX, TY = kLinTY;
     static_assert(TX * TY == 64 && kLinLds == 256, "one tile per wavefront, four per workgroup");
     const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + TZ - 1) / TZ;
     const int tile = xcd_block(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6);
@@ -325,7 +326,7 @@ pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ 
                     }
                 } else {
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) sk[lin_slot(tile, c, gz - ez0, gy - ty0, gx - tx0)] = v[c][iy][ix];
+                    for (int c = 0; c < 3; ++c) sk[lin_slot(tile, c, gz - ez0, gy - ty0, gx - tx0, TZ)] = v[c][iy][ix];
                 }
             }
     };
@@ -412,12 +413,12 @@ pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ 
 template <typename T>
 __global__ void __launch_bounds__(256)
 pa_lin_skeleton_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ sk, const Geom g,
-                       const int add) {
+                       const int TZ, const int add) {
     const int node = blockIdx.x * blockDim.x + threadIdx.x;
     if (node >= g.Nn) return;
     const int gx = node % g.Nx, r = node / g.Nx;
     const int gy = r % g.Ny, gz = r / g.Ny;
-    const int gg[3] = {gx, gy, gz}, nn[3] = {g.nx, g.ny, g.nz}, TT[3] = {kLinTX, kLinTY, kLinTZ};
+    const int gg[3] = {gx, gy, gz}, nn[3] = {g.nx, g.ny, g.nz}, TT[3] = {kLinTX, kLinTY, TZ};
     // per axis the tiles of the elements before (gg-1) and after (gg) the node
     int t_[3][2];
     bool v_[3][2];
@@ -448,7 +449,7 @@ pa_lin_skeleton_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __re
                     const int t = tx + ntx * (ty + nty * tz);
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
-                        acc[c] += sk[lin_slot(t, c, gz - tz * kLinTZ, gy - ty * kLinTY, gx - tx * kLinTX)];
+                        acc[c] += sk[lin_slot(t, c, gz - tz * TZ, gy - ty * kLinTY, gx - tx * kLinTX, TZ)];
                 }
     } else {
 #pragma unroll
@@ -474,14 +475,16 @@ int launch_lin(const ApplyLaunch& L) {
     }
     for (int qz = 0; qz < Q; ++qz)
         for (int qy = 0; qy < Q; ++qy) tb.wzy[qz * Q + qy] = (T)(L.tab->w[qz] * L.tab->w[qy]);
-    const int64_t nt = lin_tiles(g.nx, g.ny, g.nz);
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const int tz = lin_chunk(n);
+    const int64_t nt = lin_tiles(n, tz);
     const int nb = (int)((nt + 3) / 4);
     hipLaunchKernelGGL((pa_apply_lin_kernel<Q, T>), dim3(nb), dim3(256), 0, L.stream, (const T*)L.x, (T*)L.y,
-                       (T*)L.sk, (const T*)L.ed, tb, g, L.add);
+                       (T*)L.sk, (const T*)L.ed, tb, g, tz, L.add);
     PA_HIP(hipGetLastError());
     const int nb2 = (g.Nn + 255) / 256;
     hipLaunchKernelGGL((pa_lin_skeleton_kernel<T>), dim3(nb2), dim3(256), 0, L.stream, (const T*)L.x, (T*)L.y,
-                       (const T*)L.sk, g, L.add);
+                       (const T*)L.sk, g, tz, L.add);
     PA_HIP(hipGetLastError());
     return PA_OK;
 }

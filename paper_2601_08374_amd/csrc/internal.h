@@ -74,18 +74,34 @@ int launch_apply_p7(const ApplyLaunch&, int q_off, int dtype);
 int launch_apply_p8(const ApplyLaunch&, int q_off, int dtype);
 
 // Linear elements (p = 1) run a register-resident kernel in which one wavefront
-// covers kLinTX x kLinTY element columns and each lane walks kLinTZ elements up
-// its column; only nodes on the faces of such tiles go through the skeleton buffer.
-constexpr int kLinTX = 8, kLinTY = 8, kLinTZ = 4;
+// covers kLinTX x kLinTY element columns and each lane walks a chunk of lin_chunk()
+// elements up its column; only nodes on the faces of such tiles go through the
+// skeleton buffer.
+constexpr int kLinTX = 8, kLinTY = 8;
+// Wavefronts the GPU holds at once for that kernel: 256 CUs x 4 SIMDs x 2 waves.
+constexpr int kLinWaveSlots = 2048;
 
-inline int64_t lin_tiles(int nx, int ny, int nz) {
-    return (int64_t)((nx + kLinTX - 1) / kLinTX) * ((ny + kLinTY - 1) / kLinTY) * ((nz + kLinTZ - 1) / kLinTZ);
+// z-chunk length for an n[0] x n[1] x n[2] mesh: the smallest length >= 4 with which all
+// (column tile, z-chunk) wavefronts are resident at once -- one round of waves, no tail,
+// and few tile faces across z.
+inline int lin_chunk(const int n[3]) {
+    const int64_t nxy = (int64_t)((n[0] + kLinTX - 1) / kLinTX) * ((n[1] + kLinTY - 1) / kLinTY);
+    int L = 4;
+    while (L < n[2] && nxy * ((n[2] + L - 1) / L) > kLinWaveSlots) ++L;
+    return L;
+}
+
+inline int64_t lin_tiles(const int n[3], int tz) {
+    return (int64_t)((n[0] + kLinTX - 1) / kLinTX) * ((n[1] + kLinTY - 1) / kLinTY) * ((n[2] + tz - 1) / tz);
 }
 
 // Words of the skeleton buffer of one operator: per element, 3 components x its
 // element-boundary nodes; for p = 1, 3 components x the node box of every tile.
 inline int64_t skeleton_words(int p, const int n[3]) {
-    if (p == 1) return lin_tiles(n[0], n[1], n[2]) * 3 * (kLinTX + 1) * (kLinTY + 1) * (kLinTZ + 1);
+    if (p == 1) {
+        const int tz = lin_chunk(n);
+        return lin_tiles(n, tz) * 3 * (kLinTX + 1) * (kLinTY + 1) * (tz + 1);
+    }
     const int64_t NE = (int64_t)n[0] * n[1] * n[2];
     const int64_t D = p + 1;
     return NE * 3 * (D * D * D - (D - 2) * (D - 2) * (D - 2));

@@ -98,6 +98,23 @@ def test_apply_p1_tiles(q, dtype):
 
 
 @pytest.mark.parametrize("dtype", [0, 1])
+def test_apply_p1_long_chunks(dtype):
+    """Linear elements on a wide, thin mesh (400 x 400 x 5): more column tiles than the GPU holds
+    waves for, so every lane walks the whole z extent in one chunk (longer than the 4-element
+    minimum); full output against the oracle, two materials, clamped on two faces."""
+    pa = _pa()
+    print(f"p=1 long chunks dtype={dtype}", flush=True)
+    mesh = syn.BoxMesh(n=(400, 400, 5), L=(2.0, 2.0, 0.025), A=syn.SHEAR_A, clamped_faces=0b010001)
+    lam, mu = syn.two_material_lame(mesh.num_elements, seed=3)
+    x = syn.uniform_vector(mesh.num_dofs(1), seed=7)
+    op_ref = elasticity.Operator(mesh, 1, 3, lam, mu)
+    for flags, constrained in ((0, True), (1, False)):
+        ref = op_ref.apply(x, constrained=constrained)
+        y, _ = _gpu_apply(mesh, 1, 3, lam, mu, x, dtype, flags=flags)
+        assert _rel(y, ref) <= TOL[dtype], (flags, _rel(y, ref))
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
 def test_apply_add_flag_and_constrained_rows(dtype):
     pa = _pa()
     mesh = syn.graded_mesh((3, 2, 2), seed=3, clamped_faces=0b000011)
