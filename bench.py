@@ -127,6 +127,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the cantilever GMG-PCG solves")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the unfused apply variants")
     ap.add_argument("--serve", type=int, default=512,
                     help="requests in the serving stream (0 skips it)")
     ap.add_argument("--profile-apply", type=int, default=0, metavar="P",
@@ -285,6 +286,10 @@ def main(argv=None):
                 torch.cuda.empty_cache()
         result["sweep"] = sweep
 
+    if not args.no_ablation:
+        log("apply ablation")
+        from paper_2601_08374_amd import benchmarks
+        result["ablation"] = benchmarks.apply_ablation(torch, dev)
     if not args.no_solve:
         log("cantilever solves")
         from paper_2601_08374_amd import benchmarks

@@ -57,6 +57,12 @@ extern "C" {
 #define PA_UNCONSTRAINED 1    /* ignore clamped faces: y = A x                               */
 #define PA_ADD 2              /* accumulate: y += A x instead of y = A x                      */
 
+/* ---- apply variants (pa_elast_apply_variant) -------------------------------- */
+#define PA_VARIANT_FUSED 0            /* the production apply (pa_elast_apply_ex)                  */
+#define PA_VARIANT_UNFUSED_DENSE 1    /* three passes, dense gradient/action, full-tensor stress   */
+#define PA_VARIANT_UNFUSED_SF 2       /* three passes, sum-factorized gradient/action              */
+#define PA_VARIANT_UNFUSED_SF_VOIGT 3 /* as 2 with the Voigt stress form                           */
+
 /* ---- solver modes / stopping tests ----------------------------------------- */
 #define PA_SOLVE_F64 0        /* FP64 PCG with an FP64 V-cycle                                */
 #define PA_SOLVE_F32_IR 1     /* FP64 iterative refinement around an FP32 PCG + FP32 V-cycle  */
@@ -152,6 +158,17 @@ int pa_elast_apply(pa_op_t* op, const void* x, void* y);
 /* As pa_elast_apply with flags PA_UNCONSTRAINED and/or PA_ADD (async). */
 int pa_elast_apply_ex(pa_op_t* op, const void* x, void* y, int flags);
 
+/* The same operator in the unfused forms of the paper's cumulative ablation
+ * (Sec. 4.1-4.4, ablation table; baseline dataflow Alg. 1): a gradient pass, a
+ * stress pass and an action pass with operator-wide quadrature-point arrays in
+ * device memory between them, then a fixed-order assembly.  For measurement;
+ * results equal pa_elast_apply_ex up to rounding.  FP64 operators with q = p+2
+ * only (PA_EUNSUPPORTED otherwise); flags 0 or PA_UNCONSTRAINED (y is
+ * overwritten).  The first call on an operator allocates its work arrays
+ * (2 x 72 NE q^3 + 24 NE (p+1)^3 bytes and the dense basis-gradient table; freed
+ * by pa_elast_destroy; PA_ENOMEM if they do not fit).  Asynchronous on the
+ * operator's stream.  PA_VARIANT_FUSED runs pa_elast_apply_ex. */
+int pa_elast_apply_variant(pa_op_t* op, const void* x, void* y, int flags, int variant);
 /* d = diag(A) (async), the Jacobi diagonal of Sec. 3.1, from 1D-factorized
  * integrals of products of reference derivatives.  Constrained unless flags has
  * PA_UNCONSTRAINED (then clamped entries hold the true diagonal; otherwise 1).

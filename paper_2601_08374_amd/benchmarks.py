@@ -59,3 +59,44 @@ def cantilever_solves(torch, dev, ps=(4, 6, 8)):
         del x64, Ax, op
         torch.cuda.empty_cache()
     return out
+
+
+def apply_ablation(torch, dev, ps=(1, 2, 4, 8), reps=5):
+    """Cumulative ablation of the apply on the sheared box (FP64, q = p+2), in the order of the
+    paper's ablation table: unfused dense baseline -> + sum factorization -> + Voigt stress ->
+    + fusion into one kernel (the production apply).  HIP-event time per apply."""
+    import synthetic as syn
+    import paper_2601_08374_amd as pa
+    names = [("unfused_dense", pa.capi.PA_VARIANT_UNFUSED_DENSE), ("unfused_sf", pa.capi.PA_VARIANT_UNFUSED_SF),
+             ("unfused_sf_voigt", pa.capi.PA_VARIANT_UNFUSED_SF_VOIGT), ("fused", pa.capi.PA_VARIANT_FUSED)]
+    out = {"workload": "sheared box (~4.2M dofs), FP64, q=p+2, two materials; mean of "
+                       f"{reps} applies after one warm-up, HIP events"}
+    stream = torch.cuda.current_stream()
+    for p in ps:
+        mesh = syn.sheared_box_mesh(p)
+        lam, mu = syn.two_material_lame(mesh.num_elements, seed=1)
+        op = pa.Operator(mesh, p, lam, mu, q=p + 2, dtype=pa.PA_F64)
+        x = torch.tensor(syn.uniform_vector(op.N, 0), dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        rec, prev = {}, None
+        for name, v in names:
+            op.apply_variant(x, y, variant=v)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                op.apply_variant(x, y, variant=v)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) * 1e-3 / reps
+            r = {"us": round(t * 1e6, 1), "gdofs": round(op.N / t / 1e9, 3)}
+            if prev is not None:
+                r["marginal_speedup"] = round(prev / t, 2)
+            rec[name] = r
+            prev = t
+        rec["overall_speedup"] = round(rec["unfused_dense"]["us"] / rec["fused"]["us"], 1)
+        out[f"p{p}"] = rec
+        op.close()
+        del x, y
+        torch.cuda.empty_cache()
+    return out

@@ -188,6 +188,7 @@ int pa_elast_setup(const pa_mesh_t* m, int p, int q, const double* lambda, const
 void pa_elast_destroy(pa_op_t* op) {
     if (!op) return;
     if (op->cached) gmg_destroy(op->cached);
+    if (op->abl) free_ablation(op->abl);
     if (op->ed) (void)hipFree(op->ed);
     if (op->sk) (void)hipFree(op->sk);
     if (op->d_tab) (void)hipFree(op->d_tab);

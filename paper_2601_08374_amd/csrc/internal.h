@@ -107,6 +107,10 @@ inline int64_t skeleton_words(int p, const int n[3]) {
     return NE * 3 * (D * D * D - (D - 2) * (D - 2) * (D - 2));
 }
 
+// Work arrays of the unfused apply variants (ablation.hip), allocated on first use.
+struct AblationBuffers;
+void free_ablation(AblationBuffers* b);
+
 inline Geom make_geom(const MeshDesc& m, int p, bool constrained) {
     Geom g;
     g.nx = m.n[0]; g.ny = m.n[1]; g.nz = m.n[2];
@@ -132,5 +136,6 @@ struct pa_op {
     double* d_vert = nullptr;        // device vertex coordinates, x | y | z
     pa::Tables tab;                  // host copy of the tables (kernel arguments)
     pa_gmg* cached = nullptr;        // hierarchy cached by gmg_pcg_solve
+    pa::AblationBuffers* abl = nullptr;   // pa_elast_apply_variant work arrays
     pa_solve_opts_t cached_opts;
 };

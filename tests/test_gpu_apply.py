@@ -265,3 +265,49 @@ def test_apply_bitwise_reproducible(p, dtype):
     for y in outs[1:]:
         assert torch.equal(y, outs[0])
     assert bool(torch.isfinite(outs[0]).all())
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 8])
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_apply_variants_parity(p, variant):
+    """The unfused ablation forms (dense or sum-factorized gradient/action passes, full-tensor or
+    Voigt stress) compute the same operator: FP64 oracle parity, constrained and unconstrained."""
+    pa = _pa()
+    print(f"apply variant {variant} p={p}", flush=True)
+    mesh = _case_mesh(p, seed=p)
+    NE = mesh.num_elements
+    rng = np.random.default_rng(300 + p)
+    lam, mu = rng.uniform(0.2, 3.0, NE), rng.uniform(0.2, 3.0, NE)
+    x = syn.uniform_vector(mesh.num_dofs(p), seed=p + 1)
+    op_ref = elasticity.Operator(mesh, p, p + 2, lam, mu)
+    op = pa.Operator(mesh, p, lam, mu, q=p + 2, dtype=pa.PA_F64)
+    xt = torch.tensor(x, dtype=torch.float64, device="cuda")
+    for flags, constrained in ((0, True), (1, False)):
+        ref = op_ref.apply(x, constrained=constrained)
+        y = op.apply_variant(xt, variant=variant, flags=flags)
+        torch.cuda.synchronize()
+        assert _rel(y.cpu().numpy(), ref) <= TOL[0], (flags, _rel(y.cpu().numpy(), ref))
+
+
+def test_apply_variant_errors():
+    pa = _pa()
+    mesh = syn.BoxMesh(n=(2, 2, 2), clamped_faces=1)
+    ones = np.ones(8)
+    op32 = pa.Operator(mesh, 2, ones, ones, dtype=pa.PA_F32)
+    x32 = torch.zeros(op32.N, dtype=torch.float32, device="cuda")
+    with pytest.raises(pa.PaError) as e:
+        op32.apply_variant(x32, variant=pa.capi.PA_VARIANT_UNFUSED_SF)
+    assert e.value.code == pa.capi.PA_EUNSUPPORTED
+    op = pa.Operator(mesh, 2, ones, ones, q=3, dtype=pa.PA_F64)
+    x = torch.zeros(op.N, dtype=torch.float64, device="cuda")
+    with pytest.raises(pa.PaError) as e:
+        op.apply_variant(x, variant=pa.capi.PA_VARIANT_UNFUSED_DENSE)
+    assert e.value.code == pa.capi.PA_EUNSUPPORTED
+    op4 = pa.Operator(mesh, 2, ones, ones, dtype=pa.PA_F64)
+    for variant, flags, code in ((7, 0, pa.capi.PA_EINVAL), (2, pa.PA_ADD, pa.capi.PA_EUNSUPPORTED)):
+        with pytest.raises(pa.PaError) as e:
+            op4.apply_variant(x, variant=variant, flags=flags)
+        assert e.value.code == code
+    # the fused variant is the production apply
+    xr = torch.tensor(syn.uniform_vector(op4.N, 3), dtype=torch.float64, device="cuda")
+    assert torch.equal(op4.apply_variant(xr, variant=pa.capi.PA_VARIANT_FUSED), op4.apply(xr))
