@@ -115,6 +115,30 @@ def two_material_lame(num_elements: int, seed: int = 1, E=(1.0, 100.0), nu: floa
     return lame_from_young_poisson(Es, np.full(num_elements, nu))
 
 
+def random_spd_stiffness(num: int, seed: int = 11, lam: float = 1.0, mu: float = 1.0,
+                         spread: float = 0.5) -> np.ndarray:
+    """[num, 6, 6] symmetric positive definite Voigt stiffnesses: an isotropic matrix
+    (lam, mu) plus spread * M M^T / 6 with M ~ U[-1,1]^{6x6} (general anisotropy)."""
+    rng = np.random.default_rng(seed)
+    base = np.zeros((6, 6))
+    base[:3, :3] = lam
+    base += np.diag([2 * mu, 2 * mu, 2 * mu, mu, mu, mu])
+    M = rng.uniform(-1.0, 1.0, (num, 6, 6))
+    return base[None] + spread * np.einsum("nij,nkj->nik", M, M) / 6.0
+
+
+def quadrature_point_lame(lam_e, mu_e, q: int, seed: int = 13, spread: float = 0.3):
+    """Per-point Lame parameters [NE, q^3]: the element values times (1 + spread u),
+    u ~ U[-1,1] independently per point (point alpha = qx + q (qy + q qz))."""
+    rng = np.random.default_rng(seed)
+    lam_e = np.asarray(lam_e, dtype=np.float64)
+    mu_e = np.asarray(mu_e, dtype=np.float64)
+    n = lam_e.shape[0]
+    f1 = 1.0 + spread * rng.uniform(-1.0, 1.0, (n, q ** 3))
+    f2 = 1.0 + spread * rng.uniform(-1.0, 1.0, (n, q ** 3))
+    return lam_e[:, None] * f1, mu_e[:, None] * f2
+
+
 def cantilever_mesh(nx: int = 80, ny: int = 8, nz: int = 8, length: float = 8.0) -> BoxMesh:
     """8:1:1 cantilever [0,8]x[0,1]^2 clamped at x=0 (traction goes on x=8)."""
     return BoxMesh(n=(nx, ny, nz), L=(length, 1.0, 1.0), clamped_faces=1 << FACE_XMIN)
