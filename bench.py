@@ -128,6 +128,7 @@ def main(argv=None):
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the cantilever GMG-PCG solves")
     ap.add_argument("--no-ablation", action="store_true", help="skip the unfused apply variants")
+    ap.add_argument("--no-material", action="store_true", help="skip the general material data forms")
     ap.add_argument("--serve", type=int, default=512,
                     help="requests in the serving stream (0 skips it)")
     ap.add_argument("--profile-apply", type=int, default=0, metavar="P",
@@ -290,6 +291,10 @@ def main(argv=None):
         log("apply ablation")
         from paper_2601_08374_amd import benchmarks
         result["ablation"] = benchmarks.apply_ablation(torch, dev)
+    if not args.no_material:
+        log("apply with general material data")
+        from paper_2601_08374_amd import benchmarks
+        result["material"] = benchmarks.apply_material(torch, dev)
     if not args.no_solve:
         log("cantilever solves")
         from paper_2601_08374_amd import benchmarks

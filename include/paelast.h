@@ -57,6 +57,11 @@ extern "C" {
 #define PA_UNCONSTRAINED 1    /* ignore clamped faces: y = A x                               */
 #define PA_ADD 2              /* accumulate: y += A x instead of y = A x                      */
 
+/* ---- material data forms (pa_elast_setup_material) ---------------------------- */
+#define PA_MAT_ELEM_ISO 0   /* lambda, mu per element (pa_elast_setup)                           */
+#define PA_MAT_QP_ISO 1     /* lambda, mu per element and quadrature point                         */
+#define PA_MAT_ANISO 2      /* symmetric 6x6 Voigt stiffness per element                          */
+
 /* ---- apply variants (pa_elast_apply_variant) -------------------------------- */
 #define PA_VARIANT_FUSED 0            /* the production apply (pa_elast_apply_ex)                  */
 #define PA_VARIANT_UNFUSED_DENSE 1    /* three passes, dense gradient/action, full-tensor stress   */
@@ -133,6 +138,20 @@ void pa_solve_opts_default(pa_solve_opts_t* o);
  * PA_EHIP. On success *out owns all device memory; free with pa_elast_destroy. */
 int pa_elast_setup(const pa_mesh_t* m, int p, int q, const double* lambda, const double* mu,
                    int dtype, void* hip_stream, pa_op_t** out);
+/* The operator with general material data (Sec. 2.1 eq. 2; the paper's PA data holds
+ * the material at every quadrature point, Sec. 4.5).  kind = PA_MAT_QP_ISO: data is a
+ * host array [NE][q^3][2] of (lambda, mu) per element and Gauss-Legendre point, point
+ * (qx, qy, qz) at qx + q (qy + q qz), each with mu > 0 and lambda + 2 mu / 3 > 0.
+ * kind = PA_MAT_ANISO: data is a host array [NE][21], the upper triangle (row by row)
+ * of the symmetric positive definite Voigt stiffness C in sigma_V = C eps_V with
+ * eps_V = (e_xx, e_yy, e_zz, 2 e_yz, 2 e_xz, 2 e_xy).  The data is copied.  q must be
+ * p + 2 (PA_EUNSUPPORTED otherwise); other arguments and errors as pa_elast_setup
+ * (PA_EINVAL for a point or element that violates the conditions above).  apply and
+ * rhs work as for pa_elast_setup operators; pa_elast_diagonal, gmg_setup and
+ * gmg_pcg_solve return PA_EUNSUPPORTED (the hierarchy coarsens per-element Lame
+ * parameters). */
+int pa_elast_setup_material(const pa_mesh_t* m, int p, int q, int kind, const double* data, int dtype,
+                            void* hip_stream, pa_op_t** out);
 void pa_elast_destroy(pa_op_t* op);
 int pa_elast_set_stream(pa_op_t* op, void* hip_stream);
 /* N = 3 * number of nodes. */

@@ -13,10 +13,11 @@ from typing import Optional
 import numpy as np
 
 from . import capi
-from .capi import (PA_ADD, PA_F32, PA_F64, PA_SOLVE_F32_IR, PA_SOLVE_F32_PREC, PA_SOLVE_F64, PA_STOP_PREC, PA_STOP_TRUE,
+from .capi import (PA_ADD, PA_F32, PA_F64, PA_MAT_ANISO, PA_MAT_ELEM_ISO, PA_MAT_QP_ISO, PA_SOLVE_F32_IR, PA_SOLVE_F32_PREC, PA_SOLVE_F64, PA_STOP_PREC, PA_STOP_TRUE,
                    PA_UNCONSTRAINED, PaError)
 
 __all__ = ["Operator", "Hierarchy", "mesh_struct", "capi", "PA_F64", "PA_F32", "PA_UNCONSTRAINED", "PA_ADD",
+           "PA_MAT_ELEM_ISO", "PA_MAT_QP_ISO", "PA_MAT_ANISO",
            "PA_SOLVE_F64", "PA_SOLVE_F32_IR", "PA_SOLVE_F32_PREC", "PA_STOP_PREC", "PA_STOP_TRUE", "PaError", "solve_opts"]
 
 
@@ -91,11 +92,33 @@ class Operator:
         capi.check(capi.pa_elast_setup(C.byref(ms), self.p, self.q, lam.ctypes.data_as(C.POINTER(C.c_double)),
                                        mu.ctypes.data_as(C.POINTER(C.c_double)), dtype,
                                        C.c_void_p(_stream_handle(stream)), C.byref(h)))
+        self._attach(h)
+
+    def _attach(self, h):
         self.handle = h
         n = C.c_int64()
         capi.check(capi.pa_elast_ndofs(h, C.byref(n)))
         self.N = int(n.value)
         self._hier = None
+
+    @classmethod
+    def with_material(cls, mesh, p: int, kind: int, data, q: Optional[int] = None, dtype: int = PA_F64,
+                      stream=None):
+        """pa_elast_setup_material: kind PA_MAT_QP_ISO with data [NE, q^3, 2] (lambda, mu per
+        Gauss-Legendre point, point qx + q (qy + q qz)), or PA_MAT_ANISO with data [NE, 21]
+        (upper triangle of the Voigt stiffness, row by row)."""
+        self = cls.__new__(cls)
+        self.mesh, self.p, self.q = mesh, int(p), int(q if q is not None else p + 2)
+        self.dtype = dtype
+        self.stream = stream
+        d = np.ascontiguousarray(np.asarray(data, dtype=np.float64))
+        ms, keep = mesh_struct(mesh)
+        h = C.c_void_p()
+        capi.check(capi.pa_elast_setup_material(C.byref(ms), self.p, self.q, int(kind),
+                                                d.ctypes.data_as(C.POINTER(C.c_double)), dtype,
+                                                C.c_void_p(_stream_handle(stream)), C.byref(h)))
+        self._attach(h)
+        return self
 
     @property
     def torch_dtype(self):

@@ -1,8 +1,13 @@
-"""Solver benchmarks on the 8:1:1 cantilever (80x8x8 hexahedra, clamped at x=0,
-unit downward traction on x=8, E=1, nu=0.3) at p in {4,6,8}: plain FP64 GMG-PCG,
-the FP32 apply / FP32 V-cycle inside FP64 iterative refinement, and FP64 PCG
-preconditioned by the FP32 V-cycle, all to a true relative residual of 1e-8,
-with p-hierarchy down to 1 and 2 h-levels, Chebyshev(3)-Jacobi smoothing."""
+"""Benchmarks beside the operator sweep.
+
+Solver: the 8:1:1 cantilever (80x8x8 hexahedra, clamped at x=0, unit downward
+traction on x=8, E=1, nu=0.3) at p in {4,6,8}: plain FP64 GMG-PCG, the FP32 apply /
+FP32 V-cycle inside FP64 iterative refinement, and FP64 PCG preconditioned by the
+FP32 V-cycle, all to a true relative residual of 1e-8, with p-hierarchy down to 1
+and 2 h-levels, Chebyshev(3)-Jacobi smoothing.
+
+Apply: the cumulative ablation (unfused variants vs the fused kernel) and the fused
+apply with the three material data forms, on the sheared box."""
 from __future__ import annotations
 
 import time
@@ -57,6 +62,54 @@ def cantilever_solves(torch, dev, ps=(4, 6, 8)):
             out[f"p{p}"][name] = r32
             del x32, e, Ae
         del x64, Ax, op
+        torch.cuda.empty_cache()
+    return out
+
+
+def apply_material(torch, dev, ps=(1, 2, 4, 8), reps=10):
+    """The fused apply with the three material data forms on the sheared box (q = p+2):
+    per-element Lame parameters, per-quadrature-point Lame parameters and a per-element
+    anisotropic Voigt stiffness; HIP-event time per apply, FP64 and FP32."""
+    import synthetic as syn
+    import paper_2601_08374_amd as pa
+    out = {"workload": "sheared box (~4.2M dofs), q=p+2; two materials (element), +-30% per point "
+                       f"(quadrature point), random SPD Voigt stiffness (anisotropic); mean of {reps} "
+                       "applies after one warm-up, HIP events"}
+    stream = torch.cuda.current_stream()
+    for p in ps:
+        mesh = syn.sheared_box_mesh(p)
+        NE, q = mesh.num_elements, p + 2
+        lam, mu = syn.two_material_lame(NE, seed=1)
+        lq, mq = syn.quadrature_point_lame(lam, mu, q, seed=4)
+        qp = np.stack([lq, mq], axis=-1)
+        del lq, mq
+        C = syn.random_spd_stiffness(NE, seed=5)
+        c21 = np.ascontiguousarray(C[:, np.triu_indices(6)[0], np.triu_indices(6)[1]])
+        rec = {}
+        for dtype, dname in ((pa.PA_F64, "f64"), (pa.PA_F32, "f32")):
+            tdt = torch.float64 if dtype == pa.PA_F64 else torch.float32
+            for form, make in (("element_iso", lambda: pa.Operator(mesh, p, lam, mu, dtype=dtype)),
+                               ("qpoint_iso", lambda: pa.Operator.with_material(mesh, p, pa.PA_MAT_QP_ISO, qp,
+                                                                                dtype=dtype)),
+                               ("anisotropic", lambda: pa.Operator.with_material(mesh, p, pa.PA_MAT_ANISO, c21,
+                                                                                 dtype=dtype))):
+                op = make()
+                x = torch.tensor(syn.uniform_vector(op.N, 0), dtype=tdt, device=dev)
+                y = torch.empty_like(x)
+                op.apply(x, y)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(reps):
+                    op.apply(x, y)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                t = e0.elapsed_time(e1) * 1e-3 / reps
+                rec[f"{form}_{dname}"] = {"us": round(t * 1e6, 1), "gdofs": round(op.N / t / 1e9, 3)}
+                op.close()
+                del x, y
+        out[f"p{p}"] = rec
+        del qp, C, c21
         torch.cuda.empty_cache()
     return out
 

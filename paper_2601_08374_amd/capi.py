@@ -29,6 +29,9 @@ PA_VARIANT_FUSED = 0
 PA_VARIANT_UNFUSED_DENSE = 1
 PA_VARIANT_UNFUSED_SF = 2
 PA_VARIANT_UNFUSED_SF_VOIGT = 3
+PA_MAT_ELEM_ISO = 0
+PA_MAT_QP_ISO = 1
+PA_MAT_ANISO = 2
 PA_SOLVE_F64 = 0
 PA_SOLVE_F32_IR = 1
 PA_SOLVE_F32_PREC = 2
@@ -67,6 +70,7 @@ _dp = C.POINTER(C.c_double)
 SIGNATURES = {
     "pa_solve_opts_default": (None, [C.POINTER(pa_solve_opts_t)]),
     "pa_elast_setup": (_i, [C.POINTER(pa_mesh_t), _i, _i, _dp, _dp, _i, _vp, C.POINTER(_vp)]),
+    "pa_elast_setup_material": (_i, [C.POINTER(pa_mesh_t), _i, _i, _i, _dp, _i, _vp, C.POINTER(_vp)]),
     "pa_elast_destroy": (None, [_vp]),
     "pa_elast_set_stream": (_i, [_vp, _vp]),
     "pa_elast_ndofs": (_i, [_vp, C.POINTER(C.c_int64)]),

@@ -56,7 +56,7 @@ int validate_mesh(const pa_mesh_t* m, MeshDesc* out) {
 
 // Build an operator from a validated mesh description (also used for solver levels).
 int create_op(const MeshDesc& md, int p, int q, const double* lam, const double* mu, int dtype, hipStream_t s,
-              pa_op** out) {
+              pa_op** out, int mat) {
     if (p < 1) return fail(PA_EINVAL, "p = %d must be >= 1", p);
     if (p > kMaxP) return fail(PA_EUNSUPPORTED, "p = %d > %d is not built", p, kMaxP);
     if (q < p + 1 || q > p + 3) return fail(PA_EINVAL, "q = %d must be in [p+1, p+3] = [%d, %d]", q, p + 1, p + 3);
@@ -81,6 +81,7 @@ int create_op(const MeshDesc& md, int p, int q, const double* lam, const double*
     op->Nn = Nn;
     op->N = 3 * Nn;
     op->stream = s;
+    op->mat = mat;
     op->lam.assign(lam, lam + NE);
     op->mu.assign(mu, mu + NE);
     pa_solve_opts_default(&op->cached_opts);
@@ -93,7 +94,7 @@ int create_op(const MeshDesc& md, int p, int q, const double* lam, const double*
         if (rc) break;
         if (hipMalloc(&op->d_vert, nvert * sizeof(double)) != hipSuccess ||
             hipMalloc(&op->ed, (size_t)NE * kEdStride * esz) != hipSuccess ||
-            hipMalloc(&op->sk, (size_t)skeleton_words(p, md.n) * esz) != hipSuccess ||
+            hipMalloc(&op->sk, (size_t)skeleton_words(p, md.n, mat) * esz) != hipSuccess ||
             hipMalloc(&d_lm, 2 * (size_t)NE * sizeof(double)) != hipSuccess) {
             (void)hipGetLastError();
             rc = fail(PA_ENOMEM, "device allocation failed (%lld elements)", (long long)NE);
@@ -120,6 +121,42 @@ int create_op(const MeshDesc& md, int p, int q, const double* lam, const double*
     return PA_OK;
 }
 
+// Validate general material data: positive shear modulus and bulk modulus per
+// point (isotropic), positive definite Voigt stiffness per element (anisotropic,
+// by Cholesky factorisation of the unpacked upper triangle).
+int check_material(int kind, const double* data, int64_t NE, int64_t per) {
+    for (int64_t i = 0; i < NE * per; ++i)
+        if (!std::isfinite(data[i])) return fail(PA_EINVAL, "material data entry %lld is not finite", (long long)i);
+    if (kind == PA_MAT_QP_ISO) {
+        for (int64_t i = 0; i < NE * per / 2; ++i) {
+            const double l = data[2 * i], m = data[2 * i + 1];
+            if (!(m > 0.0) || !(l + 2.0 * m / 3.0 > 0.0))
+                return fail(PA_EINVAL, "element %lld point %lld: need mu > 0 and lambda + 2 mu / 3 > 0",
+                            (long long)(i / (per / 2)), (long long)(i % (per / 2)));
+        }
+        return PA_OK;
+    }
+    for (int64_t e = 0; e < NE; ++e) {
+        const double* c = data + e * 21;
+        double A[6][6];
+        for (int a = 0, k = 0; a < 6; ++a)
+            for (int b = a; b < 6; ++b, ++k) A[a][b] = A[b][a] = c[k];
+        for (int j = 0; j < 6; ++j) {
+            double d = A[j][j];
+            for (int k = 0; k < j; ++k) d -= A[j][k] * A[j][k];
+            if (!(d > 0.0))
+                return fail(PA_EINVAL, "element %lld: the Voigt stiffness is not positive definite", (long long)e);
+            A[j][j] = std::sqrt(d);
+            for (int i = j + 1; i < 6; ++i) {
+                double s = A[i][j];
+                for (int k = 0; k < j; ++k) s -= A[i][k] * A[j][k];
+                A[i][j] = s / A[j][j];
+            }
+        }
+    }
+    return PA_OK;
+}
+
 int apply_op(const pa_op* op, const void* x, void* y, int flags) {
     const bool constrained = !(flags & PA_UNCONSTRAINED);
     const int add = (flags & PA_ADD) ? 1 : 0;
@@ -129,6 +166,8 @@ int apply_op(const pa_op* op, const void* x, void* y, int flags) {
     L.y = y;
     L.sk = op->sk;
     L.ed = op->ed;
+    L.mat = op->mat;
+    L.md = op->md;
     L.tab = &op->tab;
     L.add = add;
     L.stream = op->stream;
@@ -185,11 +224,58 @@ int pa_elast_setup(const pa_mesh_t* m, int p, int q, const double* lambda, const
     return create_op(md, p, q, lambda, mu, dtype, (hipStream_t)hip_stream, out);
 }
 
+int pa_elast_setup_material(const pa_mesh_t* m, int p, int q, int kind, const double* data, int dtype,
+                            void* hip_stream, pa_op_t** out) {
+    if (!out) return fail(PA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!data) return fail(PA_EINVAL, "data is NULL");
+    if (kind != PA_MAT_QP_ISO && kind != PA_MAT_ANISO) return fail(PA_EINVAL, "material kind %d", kind);
+    MeshDesc md;
+    int rc = validate_mesh(m, &md);
+    if (rc) return rc;
+    if (p < 1) return fail(PA_EINVAL, "p = %d must be >= 1", p);
+    if (p > kMaxP) return fail(PA_EUNSUPPORTED, "p = %d > %d is not built", p, kMaxP);
+    if (q != p + 2) return fail(PA_EUNSUPPORTED, "general material data is built for q = p + 2 only");
+    if (dtype != PA_F64 && dtype != PA_F32) return fail(PA_EINVAL, "dtype %d is not PA_F64/PA_F32", dtype);
+    const int64_t NE = (int64_t)md.n[0] * md.n[1] * md.n[2];
+    const int64_t per = kind == PA_MAT_QP_ISO ? 2 * (int64_t)q * q * q : 21;
+    rc = check_material(kind, data, NE, per);
+    if (rc) return rc;
+    // unit Lame parameters: the element data then carries detJ where the kernel needs it
+    std::vector<double> one((size_t)NE, 1.0);
+    pa_op* op = nullptr;
+    rc = create_op(md, p, q, one.data(), one.data(), dtype, (hipStream_t)hip_stream, &op, kind);
+    if (rc) return rc;
+    const size_t words = (size_t)(NE * per);
+    const size_t esz = dtype == PA_F64 ? sizeof(double) : sizeof(float);
+    if (hipMalloc(&op->md, words * esz) != hipSuccess) {
+        (void)hipGetLastError();
+        op->md = nullptr;
+        pa_elast_destroy(op);
+        return fail(PA_ENOMEM, "device allocation of the material data failed");
+    }
+    hipError_t e;
+    if (dtype == PA_F64) {
+        e = hipMemcpy(op->md, data, words * esz, hipMemcpyHostToDevice);
+    } else {
+        std::vector<float> f(words);
+        for (size_t i = 0; i < words; ++i) f[i] = (float)data[i];
+        e = hipMemcpy(op->md, f.data(), words * esz, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        pa_elast_destroy(op);
+        return fail(PA_EHIP, "material upload failed: %s", hipGetErrorString(e));
+    }
+    *out = op;
+    return PA_OK;
+}
+
 void pa_elast_destroy(pa_op_t* op) {
     if (!op) return;
     if (op->cached) gmg_destroy(op->cached);
     if (op->abl) free_ablation(op->abl);
     if (op->ed) (void)hipFree(op->ed);
+    if (op->md) (void)hipFree(op->md);
     if (op->sk) (void)hipFree(op->sk);
     if (op->d_tab) (void)hipFree(op->d_tab);
     if (op->d_vert) (void)hipFree(op->d_vert);
@@ -220,6 +306,7 @@ int pa_elast_apply(pa_op_t* op, const void* x, void* y) { return pa_elast_apply_
 int pa_elast_diagonal(pa_op_t* op, void* d, int flags) {
     if (!op || !d) return fail(PA_EINVAL, "NULL argument");
     if (flags & ~PA_UNCONSTRAINED) return fail(PA_EINVAL, "unknown flags 0x%x", flags);
+    if (op->mat != PA_MAT_ELEM_ISO) return fail(PA_EUNSUPPORTED, "diagonal of general material data is not built");
     return launch_diagonal(op, d, (flags & PA_UNCONSTRAINED) ? 0 : 1);
 }
 

@@ -278,10 +278,16 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return start + k;
 }
 
-template <int P, int Q, typename T>
+// Material data forms of the pointwise stage: per-element Lame parameters (ed[9],
+// ed[10] = detJ lambda, detJ mu), per-quadrature-point Lame parameters (md =
+// [NE][Q^3][2] lambda, mu; ed[9] = detJ), or a per-element anisotropic Voigt
+// stiffness (md = [NE][21], upper triangle row by row; ed[9] = detJ).
+enum : int { kMatElemIso = 0, kMatQpIso = 1, kMatAniso = 2 };
+
+template <int P, int Q, typename T, int MAT = kMatElemIso>
 __global__ void __launch_bounds__((ApplyCfg<P, Q, T>::NT))
 pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, const T* __restrict__ ed,
-                const ApplyTabs<T, P + 1, Q> tab, const Geom g, const int add) {
+                const ApplyTabs<T, P + 1, Q> tab, const Geom g, const int add, const T* __restrict__ md) {
     using C = ApplyCfg<P, Q, T>;
     using SK = Skel<P + 1>;
     constexpr int D = P + 1, E = C::E, NT = C::NT, QQ = Q * Q;
@@ -290,6 +296,7 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
     __shared__ T Ra[E * ST];          // Y-pass output | backward Z output
     __shared__ T Ua[E * UT];          // X-pass output | backward Y output
     __shared__ T Es[E * kEdStride];   // per-element PA data of the block
+    __shared__ T Cs[MAT == kMatAniso ? E * 21 : 1];   // anisotropic stiffness of the block
     __shared__ int ebase[E];          // first node of each element, or -1 past the end
     __shared__ int ecoord[E][3];
 
@@ -312,6 +319,9 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
     }
     for (int w = tid; w < E * kEdStride; w += NT)
         Es[w] = w < ne_blk * kEdStride ? ed[(size_t)e0 * kEdStride + w] : T(0);
+    if constexpr (MAT == kMatAniso) {
+        for (int w = tid; w < E * 21; w += NT) Cs[w] = w < ne_blk * 21 ? md[(size_t)e0 * 21 + w] : T(0);
+    }
 
     const int cel = tid / QQ, cq = tid % QQ;
     const int cqx = cq % Q, cqy = cq / Q;
@@ -426,7 +436,6 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
             const T W = wxy * tab.w[k];
-            const T lam = W * lw, mu = W * mw;
             T du[3][3];   // du[c][i] = d u_c / d x_i = sum_m Jinv[m][i] ref[c][m]
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc)
@@ -434,15 +443,51 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
                 for (int i = 0; i < 3; ++i)
                     du[cc][i] = Ji[0 * 3 + i] * gq[cc][0][k] + Ji[1 * 3 + i] * gq[cc][1][k] +
                                 Ji[2 * 3 + i] * gq[cc][2][k];
-            const T div = du[0][0] + du[1][1] + du[2][2];
-            const T ld = lam * div, m2 = mu + mu;
             T s[3][3];
-            s[0][0] = ld + m2 * du[0][0];
-            s[1][1] = ld + m2 * du[1][1];
-            s[2][2] = ld + m2 * du[2][2];
-            s[0][1] = s[1][0] = mu * (du[0][1] + du[1][0]);
-            s[0][2] = s[2][0] = mu * (du[0][2] + du[2][0]);
-            s[1][2] = s[2][1] = mu * (du[1][2] + du[2][1]);
+            if constexpr (MAT == kMatAniso) {
+                // sigma_V = W detJ C eps_V, eps_V = (e_xx, e_yy, e_zz, 2e_yz, 2e_xz, 2e_xy)
+                const T* cp = Cs + cel * 21;
+                const T ev[6] = {du[0][0], du[1][1], du[2][2], du[1][2] + du[2][1], du[0][2] + du[2][0],
+                                 du[0][1] + du[1][0]};
+                const T Wd = W * lw;
+                T sv[6];
+#pragma unroll
+                for (int i = 0; i < 6; ++i) {
+                    T acc = T(0);
+#pragma unroll
+                    for (int j = 0; j < 6; ++j) {
+                        const int a = i < j ? i : j, b = i < j ? j : i;   // packed upper triangle
+                        acc += cp[a * 6 - a * (a - 1) / 2 + (b - a)] * ev[j];
+                    }
+                    sv[i] = Wd * acc;
+                }
+                s[0][0] = sv[0];
+                s[1][1] = sv[1];
+                s[2][2] = sv[2];
+                s[1][2] = s[2][1] = sv[3];
+                s[0][2] = s[2][0] = sv[4];
+                s[0][1] = s[1][0] = sv[5];
+            } else {
+                T lam, mu;
+                if constexpr (MAT == kMatQpIso) {
+                    // columns of the tail block past the last element read element e0 (lw = 0 there)
+                    const int ce = cel < ne_blk ? cel : 0;
+                    const size_t pt = ((size_t)(e0 + ce) * (Q * Q * Q) + cqx + Q * (cqy + Q * k)) * 2;
+                    lam = W * lw * md[pt];
+                    mu = W * lw * md[pt + 1];
+                } else {
+                    lam = W * lw;
+                    mu = W * mw;
+                }
+                const T div = du[0][0] + du[1][1] + du[2][2];
+                const T ld = lam * div, m2 = mu + mu;
+                s[0][0] = ld + m2 * du[0][0];
+                s[1][1] = ld + m2 * du[1][1];
+                s[2][2] = ld + m2 * du[2][2];
+                s[0][1] = s[1][0] = mu * (du[0][1] + du[1][0]);
+                s[0][2] = s[2][0] = mu * (du[0][2] + du[2][0]);
+                s[1][2] = s[2][1] = mu * (du[1][2] + du[2][1]);
+            }
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
@@ -577,14 +622,14 @@ pa_skeleton_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __restri
     }
 }
 
-template <int P, int Q, typename T>
+template <int P, int Q, typename T, int MAT = kMatElemIso>
 int launch_apply_typed(const ApplyLaunch& L) {
     using C = ApplyCfg<P, Q, T>;
     if (L.g.NE == 0) return PA_OK;
     const ApplyTabs<T, P + 1, Q> tab = make_tabs<T, P + 1, Q>(*L.tab);
     const int nb = (L.g.NE + C::E - 1) / C::E;
-    hipLaunchKernelGGL((pa_apply_kernel<P, Q, T>), dim3(nb), dim3(C::NT), 0, L.stream, (const T*)L.x, (T*)L.y,
-                       (T*)L.sk, (const T*)L.ed, tab, L.g, L.add);
+    hipLaunchKernelGGL((pa_apply_kernel<P, Q, T, MAT>), dim3(nb), dim3(C::NT), 0, L.stream, (const T*)L.x, (T*)L.y,
+                       (T*)L.sk, (const T*)L.ed, tab, L.g, L.add, (const T*)L.md);
     PA_HIP(hipGetLastError());
     const int nb2 = (L.g.Nn + 255) / 256;
     hipLaunchKernelGGL((pa_skeleton_kernel<P, T>), dim3(nb2), dim3(256), 0, L.stream, (const T*)L.x, (T*)L.y,
@@ -593,8 +638,21 @@ int launch_apply_typed(const ApplyLaunch& L) {
     return PA_OK;
 }
 
+// Per-point and anisotropic material forms (q = p + 2 only).
+template <int P>
+int launch_apply_material(const ApplyLaunch& L, int q_off, int dtype) {
+    if (q_off != 1) return fail(PA_EUNSUPPORTED, "general material data is built for q = p + 2 only");
+    if (dtype == PA_F64) {
+        if (L.mat == PA_MAT_QP_ISO) return launch_apply_typed<P, P + 2, double, kMatQpIso>(L);
+        return launch_apply_typed<P, P + 2, double, kMatAniso>(L);
+    }
+    if (L.mat == PA_MAT_QP_ISO) return launch_apply_typed<P, P + 2, float, kMatQpIso>(L);
+    return launch_apply_typed<P, P + 2, float, kMatAniso>(L);
+}
+
 template <int P>
 int launch_apply_p(const ApplyLaunch& L, int q_off, int dtype) {
+    if (L.mat != PA_MAT_ELEM_ISO) return launch_apply_material<P>(L, q_off, dtype);
     if (dtype == PA_F64) {
         switch (q_off) {
             case 0: return launch_apply_typed<P, P + 1, double>(L);

@@ -490,6 +490,8 @@ int launch_lin(const ApplyLaunch& L) {
 }
 
 int launch_apply_p1(const ApplyLaunch& L, int q_off, int dtype) {
+    // general material data goes through the sum-factorized kernel
+    if (L.mat != PA_MAT_ELEM_ISO) return launch_apply_material<1>(L, q_off, dtype);
     if (dtype == PA_F64) {
         switch (q_off) {
             case 0: return launch_lin<2, double>(L);

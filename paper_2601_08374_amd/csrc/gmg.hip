@@ -16,9 +16,6 @@
 
 namespace pa {
 
-int validate_mesh(const pa_mesh_t* m, MeshDesc* out);
-int create_op(const MeshDesc& md, int p, int q, const double* lam, const double* mu, int dtype, hipStream_t s,
-              pa_op** out);
 
 namespace {
 
@@ -784,6 +781,8 @@ extern "C" {
 int gmg_setup(pa_op_t* op, const pa_solve_opts_t* o, pa_gmg_t** out) {
     if (!op || !out) return fail(PA_EINVAL, "NULL argument");
     *out = nullptr;
+    if (op->mat != PA_MAT_ELEM_ISO)
+        return fail(PA_EUNSUPPORTED, "the multigrid hierarchy needs per-element Lame parameters");
     return setup_gmg(op, o, out);
 }
 

@@ -58,6 +58,8 @@ struct ApplyLaunch {
     void* y;
     void* sk;            // skeleton buffer of the operator (element-boundary contributions)
     const void* ed;      // per-element data of the launch dtype
+    int mat;             // PA_MAT_* form of the material data
+    const void* md;      // per-point Lame parameters or anisotropic stiffness (mat != PA_MAT_ELEM_ISO)
     const Tables* tab;
     int add;             // accumulate into y (y pre-initialised by the caller)
     hipStream_t stream;
@@ -96,9 +98,10 @@ inline int64_t lin_tiles(const int n[3], int tz) {
 }
 
 // Words of the skeleton buffer of one operator: per element, 3 components x its
-// element-boundary nodes; for p = 1, 3 components x the node box of every tile.
-inline int64_t skeleton_words(int p, const int n[3]) {
-    if (p == 1) {
+// element-boundary nodes; for p = 1 with per-element isotropic material (the
+// linear-element kernel), 3 components x the node box of every tile.
+inline int64_t skeleton_words(int p, const int n[3], int mat = PA_MAT_ELEM_ISO) {
+    if (p == 1 && mat == PA_MAT_ELEM_ISO) {
         const int tz = lin_chunk(n);
         return lin_tiles(n, tz) * 3 * (kLinTX + 1) * (kLinTY + 1) * (tz + 1);
     }
@@ -137,5 +140,7 @@ struct pa_op {
     pa::Tables tab;                  // host copy of the tables (kernel arguments)
     pa_gmg* cached = nullptr;        // hierarchy cached by gmg_pcg_solve
     pa::AblationBuffers* abl = nullptr;   // pa_elast_apply_variant work arrays
+    int mat = PA_MAT_ELEM_ISO;       // material data form
+    void* md = nullptr;              // device material data of dtype (PA_MAT_QP_ISO, PA_MAT_ANISO)
     pa_solve_opts_t cached_opts;
 };

@@ -18,6 +18,11 @@ int compute_tables(int p, int q, hipStream_t s, double** d_tab, Tables* host);
 int compute_element_data(const MeshDesc& m, const double* d_vert, const double* d_lam, const double* d_mu,
                          int dtype, void* ed, hipStream_t s);
 int launch_diagonal(const pa_op* op, void* d, int constrained);
+int validate_mesh(const pa_mesh_t* m, MeshDesc* out);
+// An operator on a validated mesh (also used for solver levels); mat sizes the
+// skeleton buffer for the kernel that serves that material form.
+int create_op(const MeshDesc& md, int p, int q, const double* lam, const double* mu, int dtype, hipStream_t s,
+              pa_op** out, int mat = PA_MAT_ELEM_ISO);
 int launch_rhs(const pa_op* op, const double f[3], int face, const double t[3], double* b, const double* d_vert);
 
 // vec.hip

@@ -1,0 +1,225 @@
+"""GPU parity of the apply with general material data (per-quadrature-point Lame
+parameters, per-element anisotropic Voigt stiffness) against the oracle's
+strain-displacement form (oracle.material.GeneralOperator).
+
+Tolerances (relative, 2-norm over the output): FP64 1e-12, FP32 1e-5, the bars of the
+apply in double and single precision.
+"""
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import material, mesh as omesh
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 1e-5}
+
+
+def _pa():
+    import paper_2601_08374_amd as pa
+    return pa
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _mesh(p, seed):
+    # several workgroup tiles with a ragged tail; graded + sheared + rotated at low p
+    rot = syn.random_rotation(seed) @ syn.SHEAR_A
+    if p <= 3:
+        return syn.graded_mesh((5, 3, 2), seed=seed, L=(1.3, 0.8, 1.0), A=rot, clamped_faces=0b010001)
+    if p <= 5:
+        return syn.graded_mesh((3, 2, 2), seed=seed, L=(1.0, 1.2, 0.9), A=rot, clamped_faces=0b000110)
+    return syn.BoxMesh(n=(3, 2, 1), L=(1.5, 1.0, 0.6), A=rot, clamped_faces=0b100000)
+
+
+def _material(kind, NE, q, seed):
+    """(data for the C ABI, Voigt stiffness for the oracle)."""
+    pa = _pa()
+    rng = np.random.default_rng(seed)
+    lam_e, mu_e = rng.uniform(0.3, 3.0, NE), rng.uniform(0.3, 3.0, NE)
+    if kind == pa.PA_MAT_QP_ISO:
+        lam, mu = syn.quadrature_point_lame(lam_e, mu_e, q, seed=seed + 1, spread=0.4)
+        return np.stack([lam, mu], axis=-1), material.isotropic_voigt(lam, mu)
+    C = syn.random_spd_stiffness(NE, seed=seed + 2, lam=1.3, mu=0.8, spread=1.0)
+    return material.packed_upper(C), C
+
+
+def _gpu(op, x, flags):
+    tdt = torch.float64 if op.dtype == 0 else torch.float32
+    y = op.apply(torch.tensor(x, dtype=tdt, device="cuda"), flags=flags)
+    torch.cuda.synchronize()
+    return y.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 8])
+@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_material_parity(p, kind, dtype):
+    pa = _pa()
+    q = p + 2
+    print(f"material parity p={p} kind={kind} dtype={dtype}", flush=True)
+    mesh = _mesh(p, seed=20 + p)
+    data, C = _material(kind, mesh.num_elements, q, seed=30 + p)
+    ref_op = material.GeneralOperator(mesh, p, q, C)
+    op = pa.Operator.with_material(mesh, p, kind, data, dtype=dtype)
+    x = syn.uniform_vector(mesh.num_dofs(p), seed=p)
+    for flags, constrained in ((0, True), (pa.PA_UNCONSTRAINED, False)):
+        ref = ref_op.apply(x, constrained=constrained)
+        y = _gpu(op, x, flags)
+        assert _rel(y, ref) <= TOL[dtype], (flags, _rel(y, ref))
+
+
+@pytest.mark.parametrize("p", [1, 2, 4, 8])
+def test_material_add_flag(p):
+    pa = _pa()
+    mesh = _mesh(p, seed=40 + p)
+    data, C = _material(pa.PA_MAT_ANISO, mesh.num_elements, p + 2, seed=50 + p)
+    op = pa.Operator.with_material(mesh, p, pa.PA_MAT_ANISO, data)
+    x = syn.uniform_vector(op.N, seed=1)
+    y0 = syn.uniform_vector(op.N, seed=2)
+    xt = torch.tensor(x, dtype=torch.float64, device="cuda")
+    yt = torch.tensor(y0, dtype=torch.float64, device="cuda")
+    op.apply(xt, yt, flags=pa.PA_ADD | pa.PA_UNCONSTRAINED)
+    ref = y0 + material.GeneralOperator(mesh, p, p + 2, C).apply(x)
+    assert _rel(yt.cpu().numpy(), ref) <= TOL[0]
+
+
+@pytest.mark.parametrize("p", [1, 3, 8])
+def test_isotropic_forms_agree(p):
+    """Per-point data constant over each element, and the isotropic Voigt matrix, give the
+    per-element operator (three kernels, one operator)."""
+    pa = _pa()
+    mesh = _mesh(p, seed=60 + p)
+    NE, q = mesh.num_elements, p + 2
+    rng = np.random.default_rng(p)
+    lam, mu = rng.uniform(0.3, 3.0, NE), rng.uniform(0.3, 3.0, NE)
+    x = syn.uniform_vector(mesh.num_dofs(p), seed=3)
+    base = _gpu(pa.Operator(mesh, p, lam, mu), x, 0)
+    qp = np.stack([np.repeat(lam[:, None], q ** 3, 1), np.repeat(mu[:, None], q ** 3, 1)], axis=-1)
+    y1 = _gpu(pa.Operator.with_material(mesh, p, pa.PA_MAT_QP_ISO, qp), x, 0)
+    y2 = _gpu(pa.Operator.with_material(mesh, p, pa.PA_MAT_ANISO,
+                                        material.packed_upper(material.isotropic_voigt(lam, mu))), x, 0)
+    assert _rel(y1, base) <= TOL[0] and _rel(y2, base) <= TOL[0]
+
+
+def _sampled_reference(mesh, p, C, x, nodes):
+    """A x at the given nodes from the elements around them (uniform Jacobian)."""
+    q, D = p + 2, p + 1
+    J = omesh.element_jacobians(syn.BoxMesh(n=(1, 1, 1), L=tuple(mesh.L[a] / mesh.n[a] for a in range(3)),
+                                            A=mesh.A))[0]
+    B, W = material.strain_matrix(p, q, J)
+    Nx, Ny, Nz = omesh.grid_shape(mesh, p)
+    Nn = Nx * Ny * Nz
+    iz, iy, ix = np.meshgrid(np.arange(D), np.arange(D), np.arange(D), indexing="ij")
+    out = []
+    for node in nodes:
+        gx, gy, gz = node % Nx, (node // Nx) % Ny, node // (Nx * Ny)
+        acc = np.zeros(3)
+        rng_x = {min(gx // p, mesh.n[0] - 1), (gx - 1) // p if gx % p == 0 and gx > 0 else -1}
+        rng_y = {min(gy // p, mesh.n[1] - 1), (gy - 1) // p if gy % p == 0 and gy > 0 else -1}
+        rng_z = {min(gz // p, mesh.n[2] - 1), (gz - 1) // p if gz % p == 0 and gz > 0 else -1}
+        for ex in rng_x:
+            for ey in rng_y:
+                for ez in rng_z:
+                    if min(ex, ey, ez) < 0:
+                        continue
+                    e = ex + mesh.n[0] * (ey + mesh.n[1] * ez)
+                    g = (ex * p + ix.ravel()) + Nx * ((ey * p + iy.ravel()) + Ny * (ez * p + iz.ravel()))
+                    xe = np.concatenate([x[c * Nn + g] for c in range(3)])
+                    Ce = C[e] if C.ndim == 4 else np.broadcast_to(C[e], (q ** 3, 6, 6))
+                    eps = np.einsum("akn,n->ak", B, xe)
+                    ye = np.einsum("akn,ak->n", B, np.einsum("akl,al->ak", Ce, eps) * W[:, None])
+                    a = (gx - ex * p) + D * ((gy - ey * p) + D * (gz - ez * p))
+                    acc += ye[[a, D ** 3 + a, 2 * D ** 3 + a]]
+        out.append(acc)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("p", [1, 2, 4, 8])
+@pytest.mark.parametrize("kind", [1, 2])
+def test_material_full_size_sampled(p, kind):
+    """The material workload at the operator sweep's full size (~4.2M dofs), same launch as
+    the benchmark: sampled outputs vs the oracle element by element around the nodes."""
+    pa = _pa()
+    print(f"material full size p={p} kind={kind}", flush=True)
+    mesh = syn.sheared_box_mesh(p)
+    NE, q = mesh.num_elements, p + 2
+    data, C = _material_full(kind, NE, q)
+    op = pa.Operator.with_material(mesh, p, kind, data)
+    x = syn.uniform_vector(op.N, seed=0)
+    y = _gpu(op, x, pa.PA_UNCONSTRAINED)
+    Nn = op.N // 3
+    nodes = np.random.default_rng(5).integers(0, Nn, 24)
+    ref = _sampled_reference(mesh, p, C, x, nodes)
+    got = np.stack([y[nodes], y[Nn + nodes], y[2 * Nn + nodes]], axis=1)
+    assert np.abs(got - ref).max() <= 50 * TOL[0] * np.abs(y).max()
+
+
+def _material_full(kind, NE, q):
+    if kind == 1:
+        lam_e, mu_e = syn.two_material_lame(NE, seed=1)
+        lam, mu = syn.quadrature_point_lame(lam_e, mu_e, q, seed=4)
+        return np.stack([lam, mu], axis=-1), _LazyIso(lam, mu)
+    C = syn.random_spd_stiffness(NE, seed=5)
+    return material.packed_upper(C), C
+
+
+class _LazyIso:
+    """Per-point isotropic Voigt matrices built on demand (the full array would not fit)."""
+
+    ndim = 4
+
+    def __init__(self, lam, mu):
+        self.lam, self.mu = lam, mu
+
+    def __getitem__(self, e):
+        return material.isotropic_voigt(self.lam[e], self.mu[e])
+
+
+def test_material_errors():
+    pa = _pa()
+    mesh = syn.BoxMesh(n=(2, 2, 2))
+    NE = 8
+    good = material.packed_upper(syn.random_spd_stiffness(NE))
+    with pytest.raises(pa.PaError) as ei:
+        pa.Operator.with_material(mesh, 2, pa.PA_MAT_ANISO, good, q=5)
+    assert ei.value.code == pa.capi.PA_EUNSUPPORTED
+    bad = good.copy()
+    bad[3, 0] = -1.0                     # C_xx < 0: not positive definite
+    with pytest.raises(pa.PaError) as ei:
+        pa.Operator.with_material(mesh, 2, pa.PA_MAT_ANISO, bad)
+    assert ei.value.code == pa.capi.PA_EINVAL
+    qp = np.ones((NE, 64, 2))
+    qp[5, 17, 1] = 0.0                   # mu = 0 at one point
+    with pytest.raises(pa.PaError) as ei:
+        pa.Operator.with_material(mesh, 2, pa.PA_MAT_QP_ISO, qp)
+    assert ei.value.code == pa.capi.PA_EINVAL
+    with pytest.raises(pa.PaError) as ei:
+        pa.Operator.with_material(mesh, 2, 7, good)
+    assert ei.value.code == pa.capi.PA_EINVAL
+    op = pa.Operator.with_material(mesh, 2, pa.PA_MAT_ANISO, good)
+    for call in (lambda: op.diagonal(), lambda: op.hierarchy(),
+                 lambda: op.apply_variant(op.empty().zero_(), variant=pa.capi.PA_VARIANT_UNFUSED_SF)):
+        with pytest.raises(pa.PaError) as ei:
+            call()
+        assert ei.value.code == pa.capi.PA_EUNSUPPORTED
+    with pytest.raises(pa.PaError) as ei:   # a mesh without elements is rejected like pa_elast_setup's
+        pa.Operator.with_material(syn.BoxMesh(n=(0, 2, 2)), 2, pa.PA_MAT_ANISO, np.zeros((0, 21)))
+    assert ei.value.code == pa.capi.PA_EINVAL
+
+
+@pytest.mark.parametrize("p", [1, 2, 8])
+@pytest.mark.parametrize("kind", [1, 2])
+def test_material_single_element(p, kind):
+    """One element (the smallest workgroup tail), all faces clamped but the top."""
+    pa = _pa()
+    mesh = syn.BoxMesh(n=(1, 1, 1), L=(0.7, 1.1, 0.9), A=syn.SHEAR_A, clamped_faces=0b011111)
+    data, C = _material(kind, 1, p + 2, seed=70 + p)
+    op = pa.Operator.with_material(mesh, p, kind, data)
+    x = syn.uniform_vector(op.N, seed=4)
+    ref = material.GeneralOperator(mesh, p, p + 2, C).apply(x, constrained=True)
+    assert _rel(_gpu(op, x, 0), ref) <= TOL[0]
