@@ -156,6 +156,32 @@ def graded_mesh(n, seed: int, L=(1.0, 1.0, 1.0), A=None, clamped_faces: int = 0,
     return BoxMesh(n=n, L=L, A=np.eye(3) if A is None else A, grade=grade, clamped_faces=clamped_faces)
 
 
+def perturbed_vertices(mesh: BoxMesh, amp: float = 0.2, seed: int = 17, interior_only: bool = True) -> np.ndarray:
+    """Vertex positions [(n0+1)(n1+1)(n2+1), 3] of a distorted box: the box vertices
+    (A X + x0, vertex (i,j,k) at i + (n0+1)(j + (n1+1)k)) moved by amp times the
+    smallest local reference spacing times U[-1,1]^3, on interior vertices only or on
+    all of them.  With amp below ~0.25 every element keeps a positive Jacobian."""
+    rng = np.random.default_rng(seed)
+    ax = [np.asarray(mesh.axis_nodes(a), dtype=np.float64) for a in range(3)]
+    Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    R = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    # smallest spacing of the reference cells touching each vertex, per axis
+    hs = []
+    for a in range(3):
+        d = np.diff(ax[a])
+        h = np.minimum(np.concatenate([[d[0]], d]), np.concatenate([d, [d[-1]]]))
+        hs.append(h)
+    Hz, Hy, Hx = np.meshgrid(hs[2], hs[1], hs[0], indexing="ij")
+    H = np.minimum(np.minimum(Hx, Hy), Hz).ravel()
+    dR = amp * H[:, None] * rng.uniform(-1.0, 1.0, R.shape)
+    if interior_only:
+        n0, n1, n2 = mesh.n
+        k, j, i = np.meshgrid(np.arange(n2 + 1), np.arange(n1 + 1), np.arange(n0 + 1), indexing="ij")
+        edge = (i == 0) | (i == n0) | (j == 0) | (j == n1) | (k == 0) | (k == n2)
+        dR[edge.ravel()] = 0.0
+    return (R + dR) @ mesh.A.T + np.asarray(mesh.x0)
+
+
 def random_rotation(seed: int) -> np.ndarray:
     """A random proper rotation matrix (QR of a Gaussian matrix, sign-fixed)."""
     rng = np.random.default_rng(seed)
