@@ -62,6 +62,11 @@ extern "C" {
 #define PA_MAT_QP_ISO 1     /* lambda, mu per element and quadrature point                         */
 #define PA_MAT_ANISO 2      /* symmetric 6x6 Voigt stiffness per element                          */
 
+/* ---- element geometry forms (pa_elast_setup_geometry) ------------------------ */
+#define PA_GEOM_AFFINE 0     /* the box map of pa_mesh_t (pa_elast_setup)                         */
+#define PA_GEOM_QP_DATA 1    /* trilinear hexahedra, J^{-1} and w det J stored per quadrature point */
+#define PA_GEOM_TRILINEAR 2  /* trilinear hexahedra, Jacobian recomputed per point (21 words/elem)  */
+
 /* ---- apply variants (pa_elast_apply_variant) -------------------------------- */
 #define PA_VARIANT_FUSED 0            /* the production apply (pa_elast_apply_ex)                  */
 #define PA_VARIANT_UNFUSED_DENSE 1    /* three passes, dense gradient/action, full-tensor stress   */
@@ -152,6 +157,23 @@ int pa_elast_setup(const pa_mesh_t* m, int p, int q, const double* lambda, const
  * parameters). */
 int pa_elast_setup_material(const pa_mesh_t* m, int p, int q, int kind, const double* data, int dtype,
                             void* hip_stream, pa_op_t** out);
+/* The operator on non-affine (trilinear) hexahedra.  The paper's kernels take affine
+ * elements with J^{-1} and det J constant per element (Sec. 4.4) and name non-affine
+ * geometry, with its trade-off between stored quadrature data and recomputation, as
+ * future work (Sec. 6); both sides of that trade-off are built here.  vertices is a host
+ * array [(n0+1)(n1+1)(n2+1)][3] of physical vertex positions, vertex (i, j, k) at
+ * i + (n0+1)(j + (n1+1)k); element (ex, ey, ez) is the trilinear image of [0,1]^3
+ * through its 8 vertices (ex+a, ey+b, ez+c).  m supplies n and clamped_faces (the faces
+ * of index-space boundaries); its box fields must be valid but do not enter the operator.
+ * kind = PA_GEOM_QP_DATA stores (J^{-1}, w det J) at every Gauss-Legendre point (10 words
+ * per point, the partial-assembly form); kind = PA_GEOM_TRILINEAR stores the 21
+ * coefficients of each element's map and recomputes J, det J and J^{-1} per point inside
+ * the apply.  q must be p + 2 (PA_EUNSUPPORTED otherwise).  lambda, mu as pa_elast_setup.
+ * PA_EINVAL if a vertex is not finite or det J <= 0 at a quadrature point of an element.
+ * apply works as for pa_elast_setup operators; pa_elast_diagonal, pa_elast_rhs,
+ * gmg_setup, gmg_pcg_solve and the unfused apply variants return PA_EUNSUPPORTED. */
+int pa_elast_setup_geometry(const pa_mesh_t* m, const double* vertices, int kind, int p, int q,
+                            const double* lambda, const double* mu, int dtype, void* hip_stream, pa_op_t** out);
 void pa_elast_destroy(pa_op_t* op);
 int pa_elast_set_stream(pa_op_t* op, void* hip_stream);
 /* N = 3 * number of nodes. */

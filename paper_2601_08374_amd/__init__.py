@@ -13,11 +13,12 @@ from typing import Optional
 import numpy as np
 
 from . import capi
-from .capi import (PA_ADD, PA_F32, PA_F64, PA_MAT_ANISO, PA_MAT_ELEM_ISO, PA_MAT_QP_ISO, PA_SOLVE_F32_IR, PA_SOLVE_F32_PREC, PA_SOLVE_F64, PA_STOP_PREC, PA_STOP_TRUE,
+from .capi import (PA_ADD, PA_F32, PA_F64, PA_GEOM_AFFINE, PA_GEOM_QP_DATA, PA_GEOM_TRILINEAR, PA_MAT_ANISO, PA_MAT_ELEM_ISO, PA_MAT_QP_ISO, PA_SOLVE_F32_IR, PA_SOLVE_F32_PREC, PA_SOLVE_F64, PA_STOP_PREC, PA_STOP_TRUE,
                    PA_UNCONSTRAINED, PaError)
 
 __all__ = ["Operator", "Hierarchy", "mesh_struct", "capi", "PA_F64", "PA_F32", "PA_UNCONSTRAINED", "PA_ADD",
-           "PA_MAT_ELEM_ISO", "PA_MAT_QP_ISO", "PA_MAT_ANISO",
+           "PA_MAT_ELEM_ISO", "PA_MAT_QP_ISO", "PA_MAT_ANISO", "PA_GEOM_AFFINE", "PA_GEOM_QP_DATA",
+           "PA_GEOM_TRILINEAR",
            "PA_SOLVE_F64", "PA_SOLVE_F32_IR", "PA_SOLVE_F32_PREC", "PA_STOP_PREC", "PA_STOP_TRUE", "PaError", "solve_opts"]
 
 
@@ -112,10 +113,40 @@ class Operator:
         self.dtype = dtype
         self.stream = stream
         d = np.ascontiguousarray(np.asarray(data, dtype=np.float64))
+        NE = int(mesh.n[0] * mesh.n[1] * mesh.n[2])
+        want = NE * (2 * self.q ** 3 if kind == PA_MAT_QP_ISO else 21)
+        if d.size != want:
+            raise ValueError(f"material data must hold {want} values, got {d.size}")
         ms, keep = mesh_struct(mesh)
         h = C.c_void_p()
         capi.check(capi.pa_elast_setup_material(C.byref(ms), self.p, self.q, int(kind),
                                                 d.ctypes.data_as(C.POINTER(C.c_double)), dtype,
+                                                C.c_void_p(_stream_handle(stream)), C.byref(h)))
+        self._attach(h)
+        return self
+
+    @classmethod
+    def with_geometry(cls, mesh, p: int, vertices, lam, mu, kind: int = PA_GEOM_TRILINEAR, q: Optional[int] = None,
+                      dtype: int = PA_F64, stream=None):
+        """pa_elast_setup_geometry: trilinear hexahedra through vertices [(n0+1)(n1+1)(n2+1), 3]
+        (vertex (i,j,k) at i + (n0+1)(j + (n1+1)k)); kind PA_GEOM_QP_DATA stores J^{-1} and
+        w det J per quadrature point, PA_GEOM_TRILINEAR recomputes them in the apply."""
+        self = cls.__new__(cls)
+        self.mesh, self.p, self.q = mesh, int(p), int(q if q is not None else p + 2)
+        self.dtype = dtype
+        self.stream = stream
+        NE = int(mesh.n[0] * mesh.n[1] * mesh.n[2])
+        v = np.ascontiguousarray(np.asarray(vertices, dtype=np.float64))
+        nv = (int(mesh.n[0]) + 1) * (int(mesh.n[1]) + 1) * (int(mesh.n[2]) + 1)
+        if v.shape != (nv, 3):
+            raise ValueError(f"vertices must be [{nv}, 3], got {v.shape}")
+        lam = np.ascontiguousarray(np.broadcast_to(np.asarray(lam, dtype=np.float64), (NE,)))
+        mu = np.ascontiguousarray(np.broadcast_to(np.asarray(mu, dtype=np.float64), (NE,)))
+        dp = C.POINTER(C.c_double)
+        ms, keep = mesh_struct(mesh)
+        h = C.c_void_p()
+        capi.check(capi.pa_elast_setup_geometry(C.byref(ms), v.ctypes.data_as(dp), int(kind), self.p, self.q,
+                                                lam.ctypes.data_as(dp), mu.ctypes.data_as(dp), dtype,
                                                 C.c_void_p(_stream_handle(stream)), C.byref(h)))
         self._attach(h)
         return self

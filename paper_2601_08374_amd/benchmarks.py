@@ -6,8 +6,9 @@ FP32 V-cycle inside FP64 iterative refinement, and FP64 PCG preconditioned by th
 FP32 V-cycle, all to a true relative residual of 1e-8, with p-hierarchy down to 1
 and 2 h-levels, Chebyshev(3)-Jacobi smoothing.
 
-Apply: the cumulative ablation (unfused variants vs the fused kernel) and the fused
-apply with the three material data forms, on the sheared box."""
+Apply: the cumulative ablation (unfused variants vs the fused kernel), the fused
+apply with the three material data forms, and the fused apply on trilinear
+(non-affine) hexahedra with stored vs recomputed geometry, on the sheared box."""
 from __future__ import annotations
 
 import time
@@ -110,6 +111,49 @@ def apply_material(torch, dev, ps=(1, 2, 4, 8), reps=10):
                 del x, y
         out[f"p{p}"] = rec
         del qp, C, c21
+        torch.cuda.empty_cache()
+    return out
+
+
+def apply_geometry(torch, dev, ps=(1, 2, 4, 8), reps=10):
+    """The fused apply on the sheared box with its interior vertices moved (trilinear
+    hexahedra): geometry stored per quadrature point (J^{-1}, w det J) vs recomputed per
+    point from 21 map coefficients per element, next to the affine box; HIP-event time
+    per apply, FP64 and FP32."""
+    import synthetic as syn
+    import paper_2601_08374_amd as pa
+    out = {"workload": "sheared box (~4.2M dofs), q=p+2, two materials; interior vertices moved by up to "
+                       f"0.2 of the spacing (seed 17); mean of {reps} applies after one warm-up, HIP events"}
+    stream = torch.cuda.current_stream()
+    for p in ps:
+        mesh = syn.sheared_box_mesh(p)
+        lam, mu = syn.two_material_lame(mesh.num_elements, seed=1)
+        verts = syn.perturbed_vertices(mesh, amp=0.2, seed=17)
+        rec = {}
+        for dtype, dname in ((pa.PA_F64, "f64"), (pa.PA_F32, "f32")):
+            tdt = torch.float64 if dtype == pa.PA_F64 else torch.float32
+            for form, make in (("affine", lambda: pa.Operator(mesh, p, lam, mu, dtype=dtype)),
+                               ("qp_data", lambda: pa.Operator.with_geometry(mesh, p, verts, lam, mu,
+                                                                             kind=pa.PA_GEOM_QP_DATA, dtype=dtype)),
+                               ("trilinear", lambda: pa.Operator.with_geometry(mesh, p, verts, lam, mu,
+                                                                               kind=pa.PA_GEOM_TRILINEAR,
+                                                                               dtype=dtype))):
+                op = make()
+                x = torch.tensor(syn.uniform_vector(op.N, 0), dtype=tdt, device=dev)
+                y = torch.empty_like(x)
+                op.apply(x, y)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(reps):
+                    op.apply(x, y)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                t = e0.elapsed_time(e1) * 1e-3 / reps
+                rec[f"{form}_{dname}"] = {"us": round(t * 1e6, 1), "gdofs": round(op.N / t / 1e9, 3)}
+                op.close()
+                del x, y
+        out[f"p{p}"] = rec
         torch.cuda.empty_cache()
     return out
 

@@ -32,6 +32,9 @@ PA_VARIANT_UNFUSED_SF_VOIGT = 3
 PA_MAT_ELEM_ISO = 0
 PA_MAT_QP_ISO = 1
 PA_MAT_ANISO = 2
+PA_GEOM_AFFINE = 0
+PA_GEOM_QP_DATA = 1
+PA_GEOM_TRILINEAR = 2
 PA_SOLVE_F64 = 0
 PA_SOLVE_F32_IR = 1
 PA_SOLVE_F32_PREC = 2
@@ -71,6 +74,7 @@ SIGNATURES = {
     "pa_solve_opts_default": (None, [C.POINTER(pa_solve_opts_t)]),
     "pa_elast_setup": (_i, [C.POINTER(pa_mesh_t), _i, _i, _dp, _dp, _i, _vp, C.POINTER(_vp)]),
     "pa_elast_setup_material": (_i, [C.POINTER(pa_mesh_t), _i, _i, _i, _dp, _i, _vp, C.POINTER(_vp)]),
+    "pa_elast_setup_geometry": (_i, [C.POINTER(pa_mesh_t), _dp, _i, _i, _i, _dp, _dp, _i, _vp, C.POINTER(_vp)]),
     "pa_elast_destroy": (None, [_vp]),
     "pa_elast_set_stream": (_i, [_vp, _vp]),
     "pa_elast_ndofs": (_i, [_vp, C.POINTER(C.c_int64)]),

@@ -461,7 +461,7 @@ extern "C" int pa_elast_apply_variant(pa_op_t* op, const void* x, void* y, int f
     if (!op || !x || !y) return fail(PA_EINVAL, "NULL argument");
     if (x == y) return fail(PA_EINVAL, "x and y must not alias");
     if (flags & ~(PA_UNCONSTRAINED | PA_ADD)) return fail(PA_EINVAL, "unknown flags 0x%x", flags);
-    if (variant != PA_VARIANT_FUSED && op->mat != PA_MAT_ELEM_ISO)
-        return fail(PA_EUNSUPPORTED, "the unfused variants take per-element Lame parameters");
+    if (variant != PA_VARIANT_FUSED && (op->mat != PA_MAT_ELEM_ISO || op->geo != PA_GEOM_AFFINE))
+        return fail(PA_EUNSUPPORTED, "the unfused variants take per-element Lame parameters on the affine box");
     return apply_variant(op, x, y, flags, variant);
 }

@@ -56,7 +56,7 @@ int validate_mesh(const pa_mesh_t* m, MeshDesc* out) {
 
 // Build an operator from a validated mesh description (also used for solver levels).
 int create_op(const MeshDesc& md, int p, int q, const double* lam, const double* mu, int dtype, hipStream_t s,
-              pa_op** out, int mat) {
+              pa_op** out, bool lin_kernel) {
     if (p < 1) return fail(PA_EINVAL, "p = %d must be >= 1", p);
     if (p > kMaxP) return fail(PA_EUNSUPPORTED, "p = %d > %d is not built", p, kMaxP);
     if (q < p + 1 || q > p + 3) return fail(PA_EINVAL, "q = %d must be in [p+1, p+3] = [%d, %d]", q, p + 1, p + 3);
@@ -81,7 +81,6 @@ int create_op(const MeshDesc& md, int p, int q, const double* lam, const double*
     op->Nn = Nn;
     op->N = 3 * Nn;
     op->stream = s;
-    op->mat = mat;
     op->lam.assign(lam, lam + NE);
     op->mu.assign(mu, mu + NE);
     pa_solve_opts_default(&op->cached_opts);
@@ -94,7 +93,7 @@ int create_op(const MeshDesc& md, int p, int q, const double* lam, const double*
         if (rc) break;
         if (hipMalloc(&op->d_vert, nvert * sizeof(double)) != hipSuccess ||
             hipMalloc(&op->ed, (size_t)NE * kEdStride * esz) != hipSuccess ||
-            hipMalloc(&op->sk, (size_t)skeleton_words(p, md.n, mat) * esz) != hipSuccess ||
+            hipMalloc(&op->sk, (size_t)skeleton_words(p, md.n, lin_kernel) * esz) != hipSuccess ||
             hipMalloc(&d_lm, 2 * (size_t)NE * sizeof(double)) != hipSuccess) {
             (void)hipGetLastError();
             rc = fail(PA_ENOMEM, "device allocation failed (%lld elements)", (long long)NE);
@@ -168,6 +167,8 @@ int apply_op(const pa_op* op, const void* x, void* y, int flags) {
     L.ed = op->ed;
     L.mat = op->mat;
     L.md = op->md;
+    L.geo = op->geo;
+    L.gd = op->gd;
     L.tab = &op->tab;
     L.add = add;
     L.stream = op->stream;
@@ -244,8 +245,9 @@ int pa_elast_setup_material(const pa_mesh_t* m, int p, int q, int kind, const do
     // unit Lame parameters: the element data then carries detJ where the kernel needs it
     std::vector<double> one((size_t)NE, 1.0);
     pa_op* op = nullptr;
-    rc = create_op(md, p, q, one.data(), one.data(), dtype, (hipStream_t)hip_stream, &op, kind);
+    rc = create_op(md, p, q, one.data(), one.data(), dtype, (hipStream_t)hip_stream, &op, false);
     if (rc) return rc;
+    op->mat = kind;
     const size_t words = (size_t)(NE * per);
     const size_t esz = dtype == PA_F64 ? sizeof(double) : sizeof(float);
     if (hipMalloc(&op->md, words * esz) != hipSuccess) {
@@ -276,6 +278,7 @@ void pa_elast_destroy(pa_op_t* op) {
     if (op->abl) free_ablation(op->abl);
     if (op->ed) (void)hipFree(op->ed);
     if (op->md) (void)hipFree(op->md);
+    if (op->gd) (void)hipFree(op->gd);
     if (op->sk) (void)hipFree(op->sk);
     if (op->d_tab) (void)hipFree(op->d_tab);
     if (op->d_vert) (void)hipFree(op->d_vert);
@@ -307,6 +310,7 @@ int pa_elast_diagonal(pa_op_t* op, void* d, int flags) {
     if (!op || !d) return fail(PA_EINVAL, "NULL argument");
     if (flags & ~PA_UNCONSTRAINED) return fail(PA_EINVAL, "unknown flags 0x%x", flags);
     if (op->mat != PA_MAT_ELEM_ISO) return fail(PA_EUNSUPPORTED, "diagonal of general material data is not built");
+    if (op->geo != PA_GEOM_AFFINE) return fail(PA_EUNSUPPORTED, "diagonal of non-affine geometry is not built");
     return launch_diagonal(op, d, (flags & PA_UNCONSTRAINED) ? 0 : 1);
 }
 
@@ -314,6 +318,7 @@ int pa_elast_rhs(pa_op_t* op, const double f[3], int traction_face, const double
     if (!op || !b) return fail(PA_EINVAL, "NULL argument");
     if (traction_face < -1 || traction_face > 5) return fail(PA_EINVAL, "traction_face %d", traction_face);
     if (traction_face >= 0 && !t) return fail(PA_EINVAL, "traction vector is NULL");
+    if (op->geo != PA_GEOM_AFFINE) return fail(PA_EUNSUPPORTED, "load vectors of non-affine geometry are not built");
     return launch_rhs(op, f, traction_face, t, b, op->d_vert);
 }
 

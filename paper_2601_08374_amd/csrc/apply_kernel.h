@@ -144,6 +144,7 @@ struct ApplyTabs {
     typename TabSel<T, D, Q>::type Bf, Gf;   // forward: nodal (D) -> quadrature (Q)
     typename TabSel<T, Q, D>::type Bt, Gt;   // backward: quadrature (Q) -> nodal (D)
     T w[Q];
+    T x[Q];   // Gauss-Legendre points on [0,1] (trilinear geometry)
 };
 
 template <typename T, int D, int Q>
@@ -160,6 +161,7 @@ inline ApplyTabs<T, D, Q> make_tabs(const Tables& t) {
     TabSel<T, Q, D>::fill(r.Bt, Bt);
     TabSel<T, Q, D>::fill(r.Gt, Gt);
     for (int k = 0; k < Q; ++k) r.w[k] = (T)t.w[k];
+    for (int k = 0; k < Q; ++k) r.x[k] = (T)t.xq[k];
     return r;
 }
 
@@ -284,10 +286,20 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // stiffness (md = [NE][21], upper triangle row by row; ed[9] = detJ).
 enum : int { kMatElemIso = 0, kMatQpIso = 1, kMatAniso = 2 };
 
-template <int P, int Q, typename T, int MAT = kMatElemIso>
+// Element geometry forms: affine (ed[0..8] = J^{-1}, constant per element), trilinear
+// with J^{-1} and w det J stored per quadrature point (gd = [NE][10][Q^3]: word
+// m*3+i is (J^{-1})_{m,i}, word 9 is w_alpha det J), or trilinear recomputed per
+// point from 21 coefficients per element (gd = [NE][21]: vectors a..g of
+// x(xi) = x0 + a xi + b eta + c zeta + d xi eta + e xi zeta + f eta zeta + g xi eta zeta).
+// The non-affine forms take ed[9], ed[10] = lambda, mu (no det J).
+enum : int { kGeoAffine = 0, kGeoQp = 1, kGeoTri = 2 };
+
+template <int P, int Q, typename T, int MAT = kMatElemIso, int GEO = kGeoAffine>
 __global__ void __launch_bounds__((ApplyCfg<P, Q, T>::NT))
 pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, const T* __restrict__ ed,
-                const ApplyTabs<T, P + 1, Q> tab, const Geom g, const int add, const T* __restrict__ md) {
+                const ApplyTabs<T, P + 1, Q> tab, const Geom g, const int add, const T* __restrict__ md,
+                const T* __restrict__ gd) {
+    static_assert(GEO == kGeoAffine || MAT == kMatElemIso, "non-affine geometry takes per-element Lame data");
     using C = ApplyCfg<P, Q, T>;
     using SK = Skel<P + 1>;
     constexpr int D = P + 1, E = C::E, NT = C::NT, QQ = Q * Q;
@@ -296,7 +308,7 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
     __shared__ T Ra[E * ST];          // Y-pass output | backward Z output
     __shared__ T Ua[E * UT];          // X-pass output | backward Y output
     __shared__ T Es[E * kEdStride];   // per-element PA data of the block
-    __shared__ T Cs[MAT == kMatAniso ? E * 21 : 1];   // anisotropic stiffness of the block
+    __shared__ T Cs[MAT == kMatAniso || GEO == kGeoTri ? E * 21 : 1];   // stiffness or trilinear coefficients
     __shared__ int ebase[E];          // first node of each element, or -1 past the end
     __shared__ int ecoord[E][3];
 
@@ -321,6 +333,10 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
         Es[w] = w < ne_blk * kEdStride ? ed[(size_t)e0 * kEdStride + w] : T(0);
     if constexpr (MAT == kMatAniso) {
         for (int w = tid; w < E * 21; w += NT) Cs[w] = w < ne_blk * 21 ? md[(size_t)e0 * 21 + w] : T(0);
+    }
+    if constexpr (GEO == kGeoTri) {
+        // slots past the last element repeat element e0 (a regular map; their Lame data is zero)
+        for (int w = tid; w < E * 21; w += NT) Cs[w] = gd[(size_t)e0 * 21 + (w < ne_blk * 21 ? w : w % 21)];
     }
 
     const int cel = tid / QQ, cq = tid % QQ;
@@ -433,9 +449,53 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
         for (int k = 0; k < 9; ++k) Ji[k] = d[k];
         const T lw = d[9], mw = d[10];
         const T wxy = tab.w[cqx] * tab.w[cqy];
+        // trilinear geometry: the parts of the Jacobian columns fixed along the column
+        // (J[:,0] = A0 + zeta A1, J[:,1] = B0 + zeta B1, J[:,2] = C0)
+        T A0[3], A1[3], B0[3], B1[3], C0[3];
+        if constexpr (GEO == kGeoTri) {
+            const T* gc = Cs + cel * 21;
+            const T xi = tab.x[cqx], eta = tab.x[cqy];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const T a = gc[i], b = gc[3 + i], c = gc[6 + i], dd = gc[9 + i], ee = gc[12 + i],
+                        f = gc[15 + i], gg = gc[18 + i];
+                A0[i] = a + dd * eta;
+                A1[i] = ee + gg * eta;
+                B0[i] = b + dd * xi;
+                B1[i] = f + gg * xi;
+                C0[i] = c + ee * xi + (f + gg * xi) * eta;
+            }
+        }
+        // columns of the tail block past the last element read element e0 (zero Lame data there)
+        const int ce = cel < ne_blk ? cel : 0;
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
-            const T W = wxy * tab.w[k];
+            T W = wxy * tab.w[k];
+            if constexpr (GEO == kGeoQp) {
+                const T* gp = gd + (size_t)(e0 + ce) * (10 * Q * Q * Q) + cqx + Q * (cqy + Q * k);
+#pragma unroll
+                for (int w = 0; w < 9; ++w) Ji[w] = gp[w * (Q * Q * Q)];
+                W = gp[9 * (Q * Q * Q)];
+            } else if constexpr (GEO == kGeoTri) {
+                // Ji = adj(J) = det J * J^{-1}; the 1/det J of both J^{-1} factors and the
+                // det J of the measure leave W / det J
+                const T z = tab.x[k];
+                const T j00 = A0[0] + z * A1[0], j10 = A0[1] + z * A1[1], j20 = A0[2] + z * A1[2];
+                const T j01 = B0[0] + z * B1[0], j11 = B0[1] + z * B1[1], j21 = B0[2] + z * B1[2];
+                const T j02 = C0[0], j12 = C0[1], j22 = C0[2];
+                // adj(J)[m][i] = cofactor of J[i][m]
+                Ji[0] = j11 * j22 - j12 * j21;
+                Ji[1] = j02 * j21 - j01 * j22;
+                Ji[2] = j01 * j12 - j02 * j11;
+                Ji[3] = j12 * j20 - j10 * j22;
+                Ji[4] = j00 * j22 - j02 * j20;
+                Ji[5] = j02 * j10 - j00 * j12;
+                Ji[6] = j10 * j21 - j11 * j20;
+                Ji[7] = j01 * j20 - j00 * j21;
+                Ji[8] = j00 * j11 - j01 * j10;
+                const T det = j00 * Ji[0] + j01 * Ji[3] + j02 * Ji[6];
+                W = W / det;
+            }
             T du[3][3];   // du[c][i] = d u_c / d x_i = sum_m Jinv[m][i] ref[c][m]
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc)
@@ -470,8 +530,6 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
             } else {
                 T lam, mu;
                 if constexpr (MAT == kMatQpIso) {
-                    // columns of the tail block past the last element read element e0 (lw = 0 there)
-                    const int ce = cel < ne_blk ? cel : 0;
                     const size_t pt = ((size_t)(e0 + ce) * (Q * Q * Q) + cqx + Q * (cqy + Q * k)) * 2;
                     lam = W * lw * md[pt];
                     mu = W * lw * md[pt + 1];
@@ -622,14 +680,14 @@ pa_skeleton_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __restri
     }
 }
 
-template <int P, int Q, typename T, int MAT = kMatElemIso>
+template <int P, int Q, typename T, int MAT = kMatElemIso, int GEO = kGeoAffine>
 int launch_apply_typed(const ApplyLaunch& L) {
     using C = ApplyCfg<P, Q, T>;
     if (L.g.NE == 0) return PA_OK;
     const ApplyTabs<T, P + 1, Q> tab = make_tabs<T, P + 1, Q>(*L.tab);
     const int nb = (L.g.NE + C::E - 1) / C::E;
-    hipLaunchKernelGGL((pa_apply_kernel<P, Q, T, MAT>), dim3(nb), dim3(C::NT), 0, L.stream, (const T*)L.x, (T*)L.y,
-                       (T*)L.sk, (const T*)L.ed, tab, L.g, L.add, (const T*)L.md);
+    hipLaunchKernelGGL((pa_apply_kernel<P, Q, T, MAT, GEO>), dim3(nb), dim3(C::NT), 0, L.stream, (const T*)L.x,
+                       (T*)L.y, (T*)L.sk, (const T*)L.ed, tab, L.g, L.add, (const T*)L.md, (const T*)L.gd);
     PA_HIP(hipGetLastError());
     const int nb2 = (L.g.Nn + 255) / 256;
     hipLaunchKernelGGL((pa_skeleton_kernel<P, T>), dim3(nb2), dim3(256), 0, L.stream, (const T*)L.x, (T*)L.y,
@@ -650,8 +708,22 @@ int launch_apply_material(const ApplyLaunch& L, int q_off, int dtype) {
     return launch_apply_typed<P, P + 2, float, kMatAniso>(L);
 }
 
+// Non-affine (trilinear) geometry forms (q = p + 2 only).
+template <int P>
+int launch_apply_geometry(const ApplyLaunch& L, int q_off, int dtype) {
+    if (q_off != 1) return fail(PA_EUNSUPPORTED, "non-affine geometry is built for q = p + 2 only");
+    if (L.mat != PA_MAT_ELEM_ISO) return fail(PA_EUNSUPPORTED, "non-affine geometry takes per-element Lame data");
+    if (dtype == PA_F64) {
+        if (L.geo == PA_GEOM_QP_DATA) return launch_apply_typed<P, P + 2, double, kMatElemIso, kGeoQp>(L);
+        return launch_apply_typed<P, P + 2, double, kMatElemIso, kGeoTri>(L);
+    }
+    if (L.geo == PA_GEOM_QP_DATA) return launch_apply_typed<P, P + 2, float, kMatElemIso, kGeoQp>(L);
+    return launch_apply_typed<P, P + 2, float, kMatElemIso, kGeoTri>(L);
+}
+
 template <int P>
 int launch_apply_p(const ApplyLaunch& L, int q_off, int dtype) {
+    if (L.geo != PA_GEOM_AFFINE) return launch_apply_geometry<P>(L, q_off, dtype);
     if (L.mat != PA_MAT_ELEM_ISO) return launch_apply_material<P>(L, q_off, dtype);
     if (dtype == PA_F64) {
         switch (q_off) {

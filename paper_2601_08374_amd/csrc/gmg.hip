@@ -365,6 +365,9 @@ void destroy_gmg(pa_gmg* G) {
 }
 
 int setup_gmg(pa_op* op, const pa_solve_opts_t* o, pa_gmg** out) {
+    if (op->mat != PA_MAT_ELEM_ISO)
+        return fail(PA_EUNSUPPORTED, "the multigrid hierarchy needs per-element Lame parameters");
+    if (op->geo != PA_GEOM_AFFINE) return fail(PA_EUNSUPPORTED, "the multigrid hierarchy needs the affine box");
     pa_solve_opts_t opts;
     if (o) opts = *o; else pa_solve_opts_default(&opts);
     if (opts.mode != PA_SOLVE_F64 && opts.mode != PA_SOLVE_F32_IR && opts.mode != PA_SOLVE_F32_PREC)
@@ -781,8 +784,6 @@ extern "C" {
 int gmg_setup(pa_op_t* op, const pa_solve_opts_t* o, pa_gmg_t** out) {
     if (!op || !out) return fail(PA_EINVAL, "NULL argument");
     *out = nullptr;
-    if (op->mat != PA_MAT_ELEM_ISO)
-        return fail(PA_EUNSUPPORTED, "the multigrid hierarchy needs per-element Lame parameters");
     return setup_gmg(op, o, out);
 }
 

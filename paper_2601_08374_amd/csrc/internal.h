@@ -60,6 +60,8 @@ struct ApplyLaunch {
     const void* ed;      // per-element data of the launch dtype
     int mat;             // PA_MAT_* form of the material data
     const void* md;      // per-point Lame parameters or anisotropic stiffness (mat != PA_MAT_ELEM_ISO)
+    int geo;             // PA_GEOM_* form of the element geometry
+    const void* gd;      // per-point J^{-1}, w det J or trilinear coefficients (geo != PA_GEOM_AFFINE)
     const Tables* tab;
     int add;             // accumulate into y (y pre-initialised by the caller)
     hipStream_t stream;
@@ -98,10 +100,10 @@ inline int64_t lin_tiles(const int n[3], int tz) {
 }
 
 // Words of the skeleton buffer of one operator: per element, 3 components x its
-// element-boundary nodes; for p = 1 with per-element isotropic material (the
-// linear-element kernel), 3 components x the node box of every tile.
-inline int64_t skeleton_words(int p, const int n[3], int mat = PA_MAT_ELEM_ISO) {
-    if (p == 1 && mat == PA_MAT_ELEM_ISO) {
+// element-boundary nodes; for the linear-element kernel (p = 1, lin_kernel),
+// 3 components x the node box of every tile.
+inline int64_t skeleton_words(int p, const int n[3], bool lin_kernel = true) {
+    if (p == 1 && lin_kernel) {
         const int tz = lin_chunk(n);
         return lin_tiles(n, tz) * 3 * (kLinTX + 1) * (kLinTY + 1) * (tz + 1);
     }
@@ -142,5 +144,7 @@ struct pa_op {
     pa::AblationBuffers* abl = nullptr;   // pa_elast_apply_variant work arrays
     int mat = PA_MAT_ELEM_ISO;       // material data form
     void* md = nullptr;              // device material data of dtype (PA_MAT_QP_ISO, PA_MAT_ANISO)
+    int geo = PA_GEOM_AFFINE;        // element geometry form
+    void* gd = nullptr;              // device geometry data of dtype (PA_GEOM_QP_DATA, PA_GEOM_TRILINEAR)
     pa_solve_opts_t cached_opts;
 };

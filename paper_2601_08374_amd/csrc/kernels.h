@@ -19,10 +19,11 @@ int compute_element_data(const MeshDesc& m, const double* d_vert, const double* 
                          int dtype, void* ed, hipStream_t s);
 int launch_diagonal(const pa_op* op, void* d, int constrained);
 int validate_mesh(const pa_mesh_t* m, MeshDesc* out);
-// An operator on a validated mesh (also used for solver levels); mat sizes the
-// skeleton buffer for the kernel that serves that material form.
+// An operator on a validated mesh (also used for solver levels).  lin_kernel: p = 1
+// applies run the linear-element kernel (per-element Lame data on the affine box);
+// false sizes the skeleton buffer for the sum-factorized kernel instead.
 int create_op(const MeshDesc& md, int p, int q, const double* lam, const double* mu, int dtype, hipStream_t s,
-              pa_op** out, int mat = PA_MAT_ELEM_ISO);
+              pa_op** out, bool lin_kernel = true);
 int launch_rhs(const pa_op* op, const double f[3], int face, const double t[3], double* b, const double* d_vert);
 
 // vec.hip
