@@ -12,10 +12,13 @@ affine map by the trilinear map of each hexahedron through its 8 vertices,
     x(xi) = sum_{a,b,c in {0,1}} N_a(xi_0) N_b(xi_1) N_c(xi_2) X_{abc},
     N_0(t) = 1 - t, N_1(t) = t on [0,1],
 
-so that J(alpha) = dx/dxi, det J(alpha) and J^{-1}(alpha) vary over the points.  The
-vertices are given as an array [(n0+1)(n1+1)(n2+1), 3] with vertex (i, j, k) at
-i + (n0+1)(j + (n1+1)k); element e = (ex, ey, ez) uses the vertices (ex+a, ey+b,
-ez+c).  Element, node and dof numbering are those of oracle.mesh.
+so that J(alpha) = dx/dxi, det J(alpha) and J^{-1}(alpha) vary over the points.  On
+the distorted box (TrilinearOperator) the vertices are given as an array
+[(n0+1)(n1+1)(n2+1), 3] with vertex (i, j, k) at i + (n0+1)(j + (n1+1)k); element
+e = (ex, ey, ez) uses the vertices (ex+a, ey+b, ez+c), and element, node and dof
+numbering are those of oracle.mesh.  On an unstructured mesh (UnstructuredOperator)
+every element lists its 8 vertices and the global node of each of its local nodes
+(an explicit element-to-node map), with arbitrary element order and orientation.
 
 The apply evaluates, element by element, the reference gradients of u at every
 point (dense basis-gradient matrices), maps them by J^{-1}(alpha), forms the
@@ -97,21 +100,22 @@ def node_coords(mesh, verts: np.ndarray, p: int) -> np.ndarray:
     return out
 
 
-class TrilinearOperator:
-    """y = A x on the distorted box with per-element Lame parameters."""
+class HexOperator:
+    """y = A x over hexahedra given by their corner vertices V8 [NE, 8, 3] (local vertex
+    a + 2(b + 2c)) and their global dofs edofs [NE, 3 D^3] (local order (c, a)), with
+    per-element Lame parameters; ess masks the clamped dofs."""
 
-    def __init__(self, mesh, p: int, q: int, verts, lam, mu):
+    def __init__(self, V8, edofs, ess, N: int, p: int, q: int, lam, mu):
         if q < p + 1:
             raise ValueError("q must be >= p+1")
-        self.mesh, self.p, self.q = mesh, int(p), int(q)
-        NE = mesh.num_elements
+        self.p, self.q, self.N = int(p), int(q), int(N)
+        NE = V8.shape[0]
+        self.NE = NE
         self.lam = np.broadcast_to(np.asarray(lam, dtype=np.float64), (NE,)).copy()
         self.mu = np.broadcast_to(np.asarray(mu, dtype=np.float64), (NE,)).copy()
-        self.N = mesh.num_dofs(p)
-        self.edofs = omesh.element_dofs(mesh, p)
-        self.ess = omesh.essential_mask(mesh, p)
+        self.edofs, self.ess = edofs, ess
         _, self.dphi, self.w = reference_basis(p, q)               # (3, D^3, Q^3), (Q^3,)
-        self.J = jacobians(element_vertices(mesh, verts), quadrature_points(q))   # [NE, Q^3, 3, 3]
+        self.J = jacobians(V8, quadrature_points(q))               # [NE, Q^3, 3, 3]
         self.detJ = np.linalg.det(self.J)
         if np.any(self.detJ <= 0):
             raise ValueError("an element has a non-positive Jacobian at a quadrature point")
@@ -129,8 +133,8 @@ class TrilinearOperator:
             x[self.ess] = 0.0
         nb = self.dphi.shape[1]
         y = np.zeros(self.N)
-        for s in range(0, self.mesh.num_elements, chunk):
-            ee = np.arange(s, min(s + chunk, self.mesh.num_elements))
+        for s in range(0, self.NE, chunk):
+            ee = np.arange(s, min(s + chunk, self.NE))
             dofs = self.edofs[ee]
             xe = x[dofs].reshape(len(ee), 3, nb)                                # [e, c, a]
             ref = np.einsum("mak,eca->ekcm", self.dphi, xe)                     # d u_c / d xi_m
@@ -156,3 +160,27 @@ class TrilinearOperator:
             A[:, j] = self.apply(e)
             e[j] = 0.0
         return A
+
+
+class TrilinearOperator(HexOperator):
+    """y = A x on the distorted box with per-element Lame parameters."""
+
+    def __init__(self, mesh, p: int, q: int, verts, lam, mu):
+        self.mesh = mesh
+        super().__init__(element_vertices(mesh, verts), omesh.element_dofs(mesh, p), omesh.essential_mask(mesh, p),
+                         mesh.num_dofs(p), p, q, lam, mu)
+
+
+class UnstructuredOperator(HexOperator):
+    """y = A x on an unstructured hexahedral mesh described by vertex positions, the 8
+    vertices of each element, the global node of each local node and a clamped-node
+    mask (the fields of synthetic.HexMesh)."""
+
+    def __init__(self, hm, q: int, lam, mu):
+        en = np.asarray(hm.elem_nodes, dtype=np.int64)
+        nn = int(hm.num_nodes)
+        V8 = np.asarray(hm.vertices, dtype=np.float64)[np.asarray(hm.elem_vertices, dtype=np.int64)]
+        edofs = np.concatenate([en + c * nn for c in range(3)], axis=1)
+        ess = np.tile(np.asarray(hm.clamped, dtype=bool), 3)
+        super().__init__(V8, edofs, ess, 3 * nn, hm.p, q, lam, mu)
+        self.hm = hm

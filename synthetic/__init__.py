@@ -182,6 +182,240 @@ def perturbed_vertices(mesh: BoxMesh, amp: float = 0.2, seed: int = 17, interior
     return (R + dR) @ mesh.A.T + np.asarray(mesh.x0)
 
 
+# ---------------------------------------------------------------- unstructured hex meshes
+# An unstructured hexahedral mesh is described by vertex positions [NV, 3], the 8
+# vertices of every element [NE, 8] (local vertex a + 2(b + 2c) at reference corner
+# (a, b, c)) and, for order p, the global node of every local node [NE, (p+1)^3]
+# (local node ix + D(iy + D iz)).  The helpers below only build such descriptions.
+
+def _cube_rotations():
+    """The 24 proper rotations of the reference cube as (perm, flip): new coordinate k
+    reads old coordinate perm[k], mirrored when flip[k]."""
+    import itertools
+    out = []
+    for perm in itertools.permutations(range(3)):
+        sign_p = np.linalg.det(np.eye(3)[list(perm)])
+        for flips in itertools.product((0, 1), repeat=3):
+            if sign_p * (-1) ** sum(flips) > 0:
+                out.append((perm, flips))
+    return out
+
+
+def hex_high_order_nodes(ev: np.ndarray, p: int, num_vertices: Optional[int] = None):
+    """Conforming global numbering of the order-p nodes of a hex mesh given only its
+    element vertices ev [NE, 8]: vertices first (node = vertex id), then edge-interior,
+    face-interior and cell-interior nodes.  Shared edges and faces are numbered in a
+    frame fixed by their global vertex ids, so neighbouring elements agree whatever
+    their local orientation.  Returns (elem_nodes [NE, D^3] int32, num_nodes)."""
+    ev = np.asarray(ev, dtype=np.int64)
+    NE = ev.shape[0]
+    NV = int(ev.max()) + 1 if num_vertices is None else int(num_vertices)
+    D, m = p + 1, p - 1
+    out = np.empty((NE, D, D, D), dtype=np.int64)      # [e, iz, iy, ix]
+    edges, faces = {}, {}
+    base_edge = NV
+
+    def corner(e, a, b, c):
+        return ev[e, a + 2 * (b + 2 * c)]
+
+    for e in range(NE):
+        for c in range(2):
+            for b in range(2):
+                for a in range(2):
+                    out[e, c * p, b * p, a * p] = corner(e, a, b, c)
+    if p == 1:
+        return out.reshape(NE, -1).astype(np.int32), NV
+    # edges: the three directions, each with 4 positions of the other two corners
+    for e in range(NE):
+        for d in range(3):
+            o1, o2 = [k for k in range(3) if k != d]
+            for s1 in range(2):
+                for s2 in range(2):
+                    lo, hi = [0, 0, 0], [0, 0, 0]
+                    lo[o1] = hi[o1] = s1
+                    lo[o2] = hi[o2] = s2
+                    hi[d] = 1
+                    vA, vB = corner(e, *lo), corner(e, *hi)
+                    key = (min(vA, vB), max(vA, vB))
+                    if key not in edges:
+                        edges[key] = len(edges)
+                    first = base_edge + edges[key] * m
+                    for t in range(1, p):
+                        tt = t if vA < vB else p - t
+                        idx = [0, 0, 0]
+                        idx[o1], idx[o2], idx[d] = s1 * p, s2 * p, t
+                        out[e, idx[2], idx[1], idx[0]] = first + tt - 1
+    base_face = base_edge + len(edges) * m
+    sq = [(0, 0), (1, 0), (1, 1), (0, 1)]           # cyclic corners of a face in its (u, v) frame
+    for e in range(NE):
+        for d in range(3):
+            u_ax, v_ax = [k for k in range(3) if k != d]
+            for s in range(2):
+                g = []
+                for (cu, cv) in sq:
+                    idx = [0, 0, 0]
+                    idx[d], idx[u_ax], idx[v_ax] = s, cu, cv
+                    g.append(corner(e, *idx))
+                key = tuple(sorted(g))
+                if key not in faces:
+                    faces[key] = len(faces)
+                first = base_face + faces[key] * m * m
+                i0 = int(np.argmin(g))                # canonical origin: the smallest vertex id
+                nxt, prv = (i0 + 1) % 4, (i0 + 3) % 4
+                i1 = nxt if g[nxt] < g[prv] else prv  # first canonical axis toward the smaller neighbour
+                o, a1 = np.array(sq[i0]), np.array(sq[i1])
+                du = a1 - o                            # local direction of canonical u
+                i2 = prv if i1 == nxt else nxt
+                dv = np.array(sq[i2]) - o              # local direction of canonical v
+                for vv in range(1, p):
+                    for uu in range(1, p):
+                        # local (u, v) of the node with canonical (uu, vv)
+                        lu = o[0] * p + du[0] * uu + dv[0] * vv
+                        lv = o[1] * p + du[1] * uu + dv[1] * vv
+                        idx = [0, 0, 0]
+                        idx[d], idx[u_ax], idx[v_ax] = s * p, lu, lv
+                        out[e, idx[2], idx[1], idx[0]] = first + (uu - 1) + m * (vv - 1)
+    base_cell = base_face + len(faces) * m * m
+    cells = base_cell + np.arange(NE)[:, None, None, None] * m ** 3
+    iz, iy, ix = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
+    out[:, 1:p, 1:p, 1:p] = cells + (ix + m * (iy + m * iz))[None]
+    return out.reshape(NE, -1).astype(np.int32), int(base_cell + NE * m ** 3)
+
+
+@dataclasses.dataclass
+class HexMesh:
+    """An unstructured hexahedral mesh of order p (see the conventions above)."""
+    vertices: np.ndarray        # [NV, 3]
+    elem_vertices: np.ndarray   # [NE, 8] int32
+    p: int
+    elem_nodes: np.ndarray      # [NE, (p+1)^3] int32
+    num_nodes: int
+    clamped: np.ndarray         # [num_nodes] bool
+
+    @property
+    def num_elements(self) -> int:
+        return self.elem_vertices.shape[0]
+
+    @property
+    def num_dofs(self) -> int:
+        return 3 * self.num_nodes
+
+
+def box_as_unstructured(mesh: BoxMesh, verts: np.ndarray, p: int, seed: int = 3, permute: bool = True,
+                        reorient: bool = True):
+    """The box mesh with vertex positions verts ([(n0+1)(n1+1)(n2+1), 3], see
+    perturbed_vertices) written as an unstructured mesh: elements in a random order,
+    each in a random one of the 24 orientations of the cube, nodes renumbered by
+    hex_high_order_nodes.  Returns (HexMesh, node_map) with node_map[u] = box node of
+    unstructured node u (box node gx + Nx (gy + Ny gz)); clamped nodes follow the box's
+    clamped faces."""
+    rng = np.random.default_rng(seed)
+    n0, n1, n2 = mesh.n
+    D = p + 1
+    NE = n0 * n1 * n2
+    ez, ey, ex = np.meshgrid(np.arange(n2), np.arange(n1), np.arange(n0), indexing="ij")
+    ex, ey, ez = ex.ravel(), ey.ravel(), ez.ravel()
+    order = rng.permutation(NE) if permute else np.arange(NE)
+    rots = _cube_rotations()
+    Nx, Ny = n0 * p + 1, n1 * p + 1
+    ev = np.empty((NE, 8), dtype=np.int64)
+    box_nodes = np.empty((NE, D ** 3), dtype=np.int64)
+    kz, ky, kx = np.meshgrid(np.arange(D), np.arange(D), np.arange(D), indexing="ij")
+    new_idx = np.stack([kx.ravel(), ky.ravel(), kz.ravel()], axis=1)     # new local coordinates
+    cz, cy, cx = np.meshgrid(np.arange(2), np.arange(2), np.arange(2), indexing="ij")
+    new_c = np.stack([cx.ravel(), cy.ravel(), cz.ravel()], axis=1)
+    for i, e in enumerate(order):
+        perm, flip = rots[rng.integers(len(rots))] if reorient else ((0, 1, 2), (0, 0, 0))
+        old = np.empty_like(new_idx)
+        oc = np.empty_like(new_c)
+        for k in range(3):
+            old[:, perm[k]] = np.where(flip[k], p - new_idx[:, k], new_idx[:, k])
+            oc[:, perm[k]] = np.where(flip[k], 1 - new_c[:, k], new_c[:, k])
+        gx, gy, gz = ex[e] * p + old[:, 0], ey[e] * p + old[:, 1], ez[e] * p + old[:, 2]
+        box_nodes[i] = gx + Nx * (gy + Ny * gz)
+        vx, vy, vz = ex[e] + oc[:, 0], ey[e] + oc[:, 1], ez[e] + oc[:, 2]
+        ev[i] = vx + (n0 + 1) * (vy + (n1 + 1) * vz)
+    en, nn = hex_high_order_nodes(ev, p, num_vertices=(n0 + 1) * (n1 + 1) * (n2 + 1))
+    node_map = np.full(nn, -1, dtype=np.int64)
+    node_map[en.ravel()] = box_nodes.ravel()
+    # clamped box faces, carried to the unstructured numbering
+    Nz = n2 * p + 1
+    g = np.arange(Nx * Ny * Nz)
+    gx, gy, gz = g % Nx, (g // Nx) % Ny, g // (Nx * Ny)
+    f = mesh.clamped_faces
+    cl = (((f & 1) > 0) & (gx == 0)) | (((f & 2) > 0) & (gx == Nx - 1)) | (((f & 4) > 0) & (gy == 0)) | \
+         (((f & 8) > 0) & (gy == Ny - 1)) | (((f & 16) > 0) & (gz == 0)) | (((f & 32) > 0) & (gz == Nz - 1))
+    hm = HexMesh(vertices=np.asarray(verts, dtype=np.float64), elem_vertices=ev.astype(np.int32), p=p,
+                 elem_nodes=en, num_nodes=nn, clamped=cl[node_map])
+    return hm, node_map
+
+
+def ogrid_cylinder(p: int, n: int = 4, m: int = 3, nz: int = 4, R: float = 1.0, a: float = 0.4,
+                   H: float = 2.0, seed: Optional[int] = None) -> HexMesh:
+    """A 5-block O-grid ("butterfly") mesh of a polygonal cylinder: a central n x n block
+    of [-a,a]^2 and four n x m blocks out to a regular 4n-gon of radius R, extruded in
+    nz layers over [0, H], clamped at z = 0.  Block corners are vertices shared by three
+    quadrilaterals of the cross-section (an unstructured topology).  Elements are listed
+    in a random order when seed is given."""
+    pts, key = [], {}
+
+    def vid(x, y):
+        k = (round(x, 12), round(y, 12))
+        if k not in key:
+            key[k] = len(pts)
+            pts.append((x, y))
+        return key[k]
+
+    quads = []
+    s = np.linspace(-a, a, n + 1)
+    for j in range(n):
+        for i in range(n):
+            quads.append((vid(s[i], s[j]), vid(s[i + 1], s[j]), vid(s[i + 1], s[j + 1]), vid(s[i], s[j + 1])))
+    # side blocks: inner edge on the square, outer edge on the polygon, counter-clockwise
+    side_in = [((a, -a), (a, a)), ((a, a), (-a, a)), ((-a, a), (-a, -a)), ((-a, -a), (a, -a))]
+    for k, (p0, p1) in enumerate(side_in):
+        th0 = -np.pi / 4 + k * np.pi / 2
+        for i in range(n):
+            for r in range(m):
+                def point(ii, rr):
+                    t = ii / n
+                    xi = (1 - t) * np.array(p0) + t * np.array(p1)
+                    th = th0 + t * np.pi / 2
+                    # polygon vertex angles are multiples of the 4n-gon's step
+                    xo = R * np.array([np.cos(th), np.sin(th)])
+                    w = rr / m
+                    q = (1 - w) * xi + w * xo
+                    return vid(q[0], q[1])
+                quads.append((point(i, r), point(i, r + 1), point(i + 1, r + 1), point(i + 1, r)))
+    P2 = np.array(pts)
+    NV2 = len(P2)
+    # orient every quadrilateral counter-clockwise
+    fixed = []
+    for qd in quads:
+        x, y = P2[list(qd), 0], P2[list(qd), 1]
+        area = 0.5 * np.sum(x * np.roll(y, -1) - np.roll(x, -1) * y)
+        fixed.append(qd if area > 0 else qd[::-1])
+    z = np.linspace(0.0, H, nz + 1)
+    V = np.concatenate([np.column_stack([P2, np.full(NV2, zz)]) for zz in z])
+    ev = []
+    for L in range(nz):
+        for (q0, q1, q2, q3) in fixed:
+            lo, hi = L * NV2, (L + 1) * NV2
+            # local vertices a + 2(b + 2c): (0,0),(1,0),(0,1),(1,1) of the quad's frame
+            ev.append((q0 + lo, q1 + lo, q3 + lo, q2 + lo, q0 + hi, q1 + hi, q3 + hi, q2 + hi))
+    ev = np.array(ev, dtype=np.int64)
+    if seed is not None:
+        ev = ev[np.random.default_rng(seed).permutation(len(ev))]
+    en, nn = hex_high_order_nodes(ev, p, num_vertices=len(V))
+    D = p + 1
+    # clamped: every node on a z = 0 face (layer-0 elements whose local iz = 0 face is the bottom)
+    cl = np.zeros(nn, dtype=bool)
+    enr = en.reshape(-1, D, D, D)
+    bottom = np.all(V[ev[:, :4], 2] == 0.0, axis=1)
+    cl[enr[bottom, 0].ravel()] = True
+    return HexMesh(vertices=V, elem_vertices=ev.astype(np.int32), p=p, elem_nodes=en, num_nodes=nn, clamped=cl)
+
+
 def random_rotation(seed: int) -> np.ndarray:
     """A random proper rotation matrix (QR of a Gaussian matrix, sign-fixed)."""
     rng = np.random.default_rng(seed)
