@@ -130,6 +130,7 @@ def main(argv=None):
     ap.add_argument("--no-ablation", action="store_true", help="skip the unfused apply variants")
     ap.add_argument("--no-material", action="store_true", help="skip the general material data forms")
     ap.add_argument("--no-geometry", action="store_true", help="skip the non-affine geometry forms")
+    ap.add_argument("--no-unstructured", action="store_true", help="skip the unstructured-mesh apply")
     ap.add_argument("--serve", type=int, default=512,
                     help="requests in the serving stream (0 skips it)")
     ap.add_argument("--profile-apply", type=int, default=0, metavar="P",
@@ -300,6 +301,10 @@ def main(argv=None):
         log("apply on non-affine geometry")
         from paper_2601_08374_amd import benchmarks
         result["geometry"] = benchmarks.apply_geometry(torch, dev)
+    if not args.no_unstructured:
+        log("apply on unstructured meshes")
+        from paper_2601_08374_amd import benchmarks
+        result["unstructured"] = benchmarks.apply_unstructured(torch, dev)
     if not args.no_solve:
         log("cantilever solves")
         from paper_2601_08374_amd import benchmarks

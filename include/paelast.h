@@ -174,6 +174,26 @@ int pa_elast_setup_material(const pa_mesh_t* m, int p, int q, int kind, const do
  * gmg_setup, gmg_pcg_solve and the unfused apply variants return PA_EUNSUPPORTED. */
 int pa_elast_setup_geometry(const pa_mesh_t* m, const double* vertices, int kind, int p, int q,
                             const double* lambda, const double* mu, int dtype, void* hip_stream, pa_op_t** out);
+/* The operator on an unstructured hexahedral mesh given by an explicit element-to-node
+ * map (the box of pa_elast_setup generalised; elements in any order and orientation).
+ * vertices: host [num_vertices][3] positions; elem_vertices: host [num_elements][8]
+ * vertex indices, local vertex a + 2(b + 2c) at reference corner (a, b, c) of [0,1]^3
+ * (the element is the trilinear image of [0,1]^3; its Jacobian is recomputed at every
+ * point as for PA_GEOM_TRILINEAR); elem_nodes: host [num_elements][(p+1)^3] global node
+ * of local node ix + (p+1)(iy + (p+1) iz), nodes at the GLL points of the element's
+ * reference axes; clamped: host [num_nodes] flags of the essential nodes (all three
+ * components), or NULL.  Dofs are component blocks c*num_nodes + node.  The map must be
+ * conforming: a local node strictly inside an element belongs to no other element
+ * (PA_EINVAL otherwise, as for an index out of range, a node listed twice in one element,
+ * a non-finite vertex or det J <= 0 at a quadrature point).  The arrays are copied.
+ * q must be p + 2 (PA_EUNSUPPORTED otherwise); lambda, mu per element as pa_elast_setup.
+ * Element-boundary contributions are summed per node in a fixed order (deterministic).
+ * apply works as for pa_elast_setup operators; pa_elast_diagonal, pa_elast_rhs,
+ * gmg_setup, gmg_pcg_solve and the unfused apply variants return PA_EUNSUPPORTED. */
+int pa_elast_setup_unstructured(int64_t num_vertices, const double* vertices, int64_t num_elements,
+                                const int32_t* elem_vertices, int64_t num_nodes, const int32_t* elem_nodes,
+                                const uint8_t* clamped, int p, int q, const double* lambda, const double* mu,
+                                int dtype, void* hip_stream, pa_op_t** out);
 void pa_elast_destroy(pa_op_t* op);
 int pa_elast_set_stream(pa_op_t* op, void* hip_stream);
 /* N = 3 * number of nodes. */

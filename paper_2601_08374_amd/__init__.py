@@ -126,6 +126,37 @@ class Operator:
         return self
 
     @classmethod
+    def unstructured(cls, hm, lam, mu, q: Optional[int] = None, dtype: int = PA_F64, stream=None):
+        """pa_elast_setup_unstructured from a mesh description with the fields vertices
+        [NV, 3], elem_vertices [NE, 8], p, elem_nodes [NE, (p+1)^3], num_nodes and clamped
+        [num_nodes] (e.g. synthetic.HexMesh)."""
+        self = cls.__new__(cls)
+        self.mesh, self.p = hm, int(hm.p)
+        self.q = int(q if q is not None else self.p + 2)
+        self.dtype = dtype
+        self.stream = stream
+        V = np.ascontiguousarray(np.asarray(hm.vertices, dtype=np.float64))
+        ev = np.ascontiguousarray(np.asarray(hm.elem_vertices, dtype=np.int32))
+        en = np.ascontiguousarray(np.asarray(hm.elem_nodes, dtype=np.int32))
+        NE, nn = ev.shape[0], int(hm.num_nodes)
+        D = self.p + 1
+        if V.ndim != 2 or V.shape[1] != 3 or ev.shape != (NE, 8) or en.shape != (NE, D ** 3):
+            raise ValueError("vertices [NV,3], elem_vertices [NE,8] and elem_nodes [NE,(p+1)^3] expected")
+        cl = None if hm.clamped is None else np.ascontiguousarray(np.asarray(hm.clamped, dtype=np.uint8))
+        if cl is not None and cl.shape != (nn,):
+            raise ValueError(f"clamped must be [{nn}]")
+        lam = np.ascontiguousarray(np.broadcast_to(np.asarray(lam, dtype=np.float64), (NE,)))
+        mu = np.ascontiguousarray(np.broadcast_to(np.asarray(mu, dtype=np.float64), (NE,)))
+        dp, ip = C.POINTER(C.c_double), C.POINTER(C.c_int32)
+        h = C.c_void_p()
+        capi.check(capi.pa_elast_setup_unstructured(
+            V.shape[0], V.ctypes.data_as(dp), NE, ev.ctypes.data_as(ip), nn, en.ctypes.data_as(ip),
+            None if cl is None else cl.ctypes.data_as(C.POINTER(C.c_uint8)), self.p, self.q,
+            lam.ctypes.data_as(dp), mu.ctypes.data_as(dp), dtype, C.c_void_p(_stream_handle(stream)), C.byref(h)))
+        self._attach(h)
+        return self
+
+    @classmethod
     def with_geometry(cls, mesh, p: int, vertices, lam, mu, kind: int = PA_GEOM_TRILINEAR, q: Optional[int] = None,
                       dtype: int = PA_F64, stream=None):
         """pa_elast_setup_geometry: trilinear hexahedra through vertices [(n0+1)(n1+1)(n2+1), 3]

@@ -7,8 +7,9 @@ FP32 V-cycle, all to a true relative residual of 1e-8, with p-hierarchy down to 
 and 2 h-levels, Chebyshev(3)-Jacobi smoothing.
 
 Apply: the cumulative ablation (unfused variants vs the fused kernel), the fused
-apply with the three material data forms, and the fused apply on trilinear
-(non-affine) hexahedra with stored vs recomputed geometry, on the sheared box."""
+apply with the three material data forms, the fused apply on trilinear
+(non-affine) hexahedra with stored vs recomputed geometry, and the fused apply on the
+same geometry given as an unstructured mesh, on the sheared box."""
 from __future__ import annotations
 
 import time
@@ -154,6 +155,55 @@ def apply_geometry(torch, dev, ps=(1, 2, 4, 8), reps=10):
                 op.close()
                 del x, y
         out[f"p{p}"] = rec
+        torch.cuda.empty_cache()
+    return out
+
+
+def apply_unstructured(torch, dev, ps=(1, 2, 4, 8), reps=10):
+    """The fused apply on the distorted sheared box given as an unstructured mesh
+    (explicit element-to-node map, every element in a random orientation), in box order
+    and with elements and nodes shuffled at random (no locality), next to the structured
+    trilinear operator on the same geometry; HIP-event time per apply."""
+    import synthetic as syn
+    import paper_2601_08374_amd as pa
+    out = {"workload": "sheared box (~4.2M dofs), q=p+2, two materials, interior vertices moved by up to 0.2 "
+                       "of the spacing; unstructured: random orientation per element, box order ('ordered') or "
+                       f"random element and node order ('shuffled'); mean of {reps} applies after one warm-up"}
+    stream = torch.cuda.current_stream()
+
+    def timed(op, tdt):
+        x = torch.tensor(syn.uniform_vector(op.N, 0), dtype=tdt, device=dev)
+        y = torch.empty_like(x)
+        op.apply(x, y)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            op.apply(x, y)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3 / reps
+        op.close()
+        return {"us": round(t * 1e6, 1), "gdofs": round(op.N / t / 1e9, 3)}
+
+    for p in ps:
+        mesh = syn.sheared_box_mesh(p)
+        lam, mu = syn.two_material_lame(mesh.num_elements, seed=1)
+        verts = syn.perturbed_vertices(mesh, amp=0.2, seed=17)
+        rec = {}
+        hm, _, order = syn.box_as_unstructured(mesh, verts, p, seed=1, permute=False, renumber=False)
+        hs, _, order_s = syn.box_as_unstructured(mesh, verts, p, seed=2, permute=True, renumber=False,
+                                                 shuffle_nodes=True)
+        for dtype, dname in ((pa.PA_F64, "f64"), (pa.PA_F32, "f32")):
+            tdt = torch.float64 if dtype == pa.PA_F64 else torch.float32
+            rec[f"structured_trilinear_{dname}"] = timed(
+                pa.Operator.with_geometry(mesh, p, verts, lam, mu, kind=pa.PA_GEOM_TRILINEAR, dtype=dtype), tdt)
+            rec[f"unstructured_ordered_{dname}"] = timed(
+                pa.Operator.unstructured(hm, lam[order], mu[order], dtype=dtype), tdt)
+            rec[f"unstructured_shuffled_{dname}"] = timed(
+                pa.Operator.unstructured(hs, lam[order_s], mu[order_s], dtype=dtype), tdt)
+        out[f"p{p}"] = rec
+        del hm, hs
         torch.cuda.empty_cache()
     return out
 

@@ -75,6 +75,9 @@ SIGNATURES = {
     "pa_elast_setup": (_i, [C.POINTER(pa_mesh_t), _i, _i, _dp, _dp, _i, _vp, C.POINTER(_vp)]),
     "pa_elast_setup_material": (_i, [C.POINTER(pa_mesh_t), _i, _i, _i, _dp, _i, _vp, C.POINTER(_vp)]),
     "pa_elast_setup_geometry": (_i, [C.POINTER(pa_mesh_t), _dp, _i, _i, _i, _dp, _dp, _i, _vp, C.POINTER(_vp)]),
+    "pa_elast_setup_unstructured": (_i, [C.c_int64, _dp, C.c_int64, C.POINTER(C.c_int32), C.c_int64,
+                                         C.POINTER(C.c_int32), C.POINTER(C.c_uint8), _i, _i, _dp, _dp, _i, _vp,
+                                         C.POINTER(_vp)]),
     "pa_elast_destroy": (None, [_vp]),
     "pa_elast_set_stream": (_i, [_vp, _vp]),
     "pa_elast_ndofs": (_i, [_vp, C.POINTER(C.c_int64)]),

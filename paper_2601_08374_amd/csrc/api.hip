@@ -160,7 +160,23 @@ int apply_op(const pa_op* op, const void* x, void* y, int flags) {
     const bool constrained = !(flags & PA_UNCONSTRAINED);
     const int add = (flags & PA_ADD) ? 1 : 0;
     ApplyLaunch L;
-    L.g = make_geom(op->mesh, op->p, constrained);
+    if (op->kmap) {
+        // unstructured mesh: only NE, Nn and the constrained flag are read
+        Geom g{};
+        g.nx = (int)op->NE; g.ny = g.nz = 1;
+        g.Nx = (int)op->Nn; g.Ny = g.Nz = 1;
+        g.Nn = (int)op->Nn;
+        g.NE = (int)op->NE;
+        g.clamp = constrained ? 1u : 0u;
+        L.g = g;
+        L.kmap = op->kmap;
+        L.sk_ptr = op->sk_ptr;
+        L.sk_idx = op->sk_idx;
+        L.sk_node = op->sk_node;
+        L.n_sk = op->n_sk;
+    } else {
+        L.g = make_geom(op->mesh, op->p, constrained);
+    }
     L.x = x;
     L.y = y;
     L.sk = op->sk;
@@ -279,6 +295,8 @@ void pa_elast_destroy(pa_op_t* op) {
     if (op->ed) (void)hipFree(op->ed);
     if (op->md) (void)hipFree(op->md);
     if (op->gd) (void)hipFree(op->gd);
+    for (int* a : {op->kmap, op->sk_ptr, op->sk_idx, op->sk_node})
+        if (a) (void)hipFree(a);
     if (op->sk) (void)hipFree(op->sk);
     if (op->d_tab) (void)hipFree(op->d_tab);
     if (op->d_vert) (void)hipFree(op->d_vert);

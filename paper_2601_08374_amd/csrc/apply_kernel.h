@@ -174,7 +174,7 @@ struct Skel {
     static constexpr int P = D - 1;
     static constexpr int S = D * D * D - (D - 2) * (D - 2) * (D - 2);
     static constexpr int LAYER = 4 * (D - 1);
-    __device__ __forceinline__ static int index(int ix, int iy, int iz) {
+    __host__ __device__ __forceinline__ static int index(int ix, int iy, int iz) {
         int base, off;
         if (iz == 0 || iz == P) {
             base = (iz == 0) ? 0 : D * D + (D - 2) * LAYER;
@@ -187,7 +187,7 @@ struct Skel {
         }
         return base + off;
     }
-    __device__ __forceinline__ static bool interior(int ix, int iy, int iz) {
+    __host__ __device__ __forceinline__ static bool interior(int ix, int iy, int iz) {
         return ix > 0 && ix < P && iy > 0 && iy < P && iz > 0 && iz < P;
     }
     // Buffer layout: node-major ([c][s][e]) up to p = 5, so that the skeleton kernel's
@@ -294,12 +294,17 @@ enum : int { kMatElemIso = 0, kMatQpIso = 1, kMatAniso = 2 };
 // The non-affine forms take ed[9], ed[10] = lambda, mu (no det J).
 enum : int { kGeoAffine = 0, kGeoQp = 1, kGeoTri = 2 };
 
-template <int P, int Q, typename T, int MAT = kMatElemIso, int GEO = kGeoAffine>
+// UNS: unstructured mesh.  Nodes come from the element-to-node map kmap (global node,
+// kClampBit on clamped nodes; g.clamp != 0 for a constrained apply), element-interior
+// nodes go to y directly and element-boundary nodes to the element-major skeleton
+// buffer, which pa_uns_gather_kernel sums per node.
+template <int P, int Q, typename T, int MAT = kMatElemIso, int GEO = kGeoAffine, bool UNS = false>
 __global__ void __launch_bounds__((ApplyCfg<P, Q, T>::NT))
 pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, const T* __restrict__ ed,
                 const ApplyTabs<T, P + 1, Q> tab, const Geom g, const int add, const T* __restrict__ md,
-                const T* __restrict__ gd) {
+                const T* __restrict__ gd, const int* __restrict__ kmap) {
     static_assert(GEO == kGeoAffine || MAT == kMatElemIso, "non-affine geometry takes per-element Lame data");
+    static_assert(!UNS || GEO == kGeoTri, "unstructured meshes take the recomputed trilinear geometry");
     using C = ApplyCfg<P, Q, T>;
     using SK = Skel<P + 1>;
     constexpr int D = P + 1, E = C::E, NT = C::NT, QQ = Q * Q;
@@ -318,7 +323,9 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
     const int ne_blk = g.NE - e0 < E ? g.NE - e0 : E;
     if (tid < E) {
         const int e = e0 + tid;
-        if (e < g.NE) {
+        if (UNS) {
+            ebase[tid] = e < g.NE ? 0 : -1;
+        } else if (e < g.NE) {
             const int ex = e % g.nx, r = e / g.nx;
             const int ey = r % g.ny, ez = r / g.ny;
             ecoord[tid][0] = ex * P;
@@ -353,6 +360,7 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
     static_assert(GX * D <= 32, "clamp mask bits");
     int ln_node[GX];       // global node of (ix = 0) of the line, or -1
     unsigned ln_cl = 0u;   // bit j*D + ix: clamped node (read as 0)
+    int ln_nodes[UNS ? GX : 1][UNS ? D : 1];   // unstructured: every node of the line
     __syncthreads();       // ebase, ecoord, Es ready
 #pragma unroll
     for (int j = 0; j < GX; ++j) {
@@ -362,7 +370,16 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
             const int el = l / (D * D), r = l % (D * D);
             const int iz = r / D, iy = r % D;
             const int b = ebase[el];
-            if (b >= 0) {
+            if (UNS && b >= 0) {
+                ln_node[j] = 0;
+                const int* mp = kmap + (size_t)(e0 + el) * (D * D * D) + D * (iy + D * iz);
+#pragma unroll
+                for (int ix = 0; ix < D; ++ix) {
+                    const unsigned v = (unsigned)mp[ix];
+                    ln_nodes[UNS ? j : 0][UNS ? ix : 0] = (int)(v & ~kClampBit);
+                    if (g.clamp && (v & kClampBit)) ln_cl |= 1u << (j * D + ix);
+                }
+            } else if (b >= 0) {
                 ln_node[j] = b + g.Nx * (iy + g.Ny * iz);
                 if (g.clamp) {
 #pragma unroll
@@ -379,7 +396,9 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
         for (int j = 0; j < GX; ++j)
 #pragma unroll
             for (int ix = 0; ix < D; ++ix)
-                xr[j][ix] = (ln_node[j] >= 0 && !((ln_cl >> (j * D + ix)) & 1u)) ? x[c * NN + ln_node[j] + ix] : T(0);
+                xr[j][ix] = (ln_node[j] >= 0 && !((ln_cl >> (j * D + ix)) & 1u))
+                                ? x[c * NN + (UNS ? (size_t)ln_nodes[UNS ? j : 0][UNS ? ix : 0] : ln_node[j] + ix)]
+                                : T(0);
     };
     line_load(0);
 
@@ -610,7 +629,16 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
                 eo_contract2<-1, 1>(a0, tab.Gt, a1, tab.Bt, yo);
 #pragma unroll
                 for (int ix = 0; ix < D; ++ix) {
-                    if (SK::interior(ix, iy, iz)) {
+                    if constexpr (UNS) {
+                        if (SK::interior(ix, iy, iz)) {
+                            // sole owner; a clamped interior node keeps its input in a constrained apply
+                            const size_t o = c * NN + ln_nodes[j][ix];
+                            const T v = ((ln_cl >> (j * D + ix)) & 1u) ? x[o] : yo[ix];
+                            y[o] = add ? y[o] + v : v;
+                        } else {
+                            sk[((size_t)(e0 + el) * 3 + c) * SK::S + SK::index(ix, iy, iz)] = yo[ix];
+                        }
+                    } else if (SK::interior(ix, iy, iz)) {
                         T* yp = y + c * NN + ln_node[j] + ix;
                         *yp = add ? *yp + yo[ix] : yo[ix];
                     } else {
@@ -680,15 +708,58 @@ pa_skeleton_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __restri
     }
 }
 
-template <int P, int Q, typename T, int MAT = kMatElemIso, int GEO = kGeoAffine>
+// Unstructured mesh: every non-interior node i sums its skeleton entries in the fixed
+// order of its list (element, then slot ascending) and writes y; a clamped node keeps
+// its input in a constrained apply, a node of no element gets 0.
+template <typename T>
+__global__ void __launch_bounds__(256)
+pa_uns_gather_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ sk,
+                     const int* __restrict__ ptr, const int* __restrict__ idx, const int* __restrict__ nodes,
+                     const int n_sk, const int S, const size_t NN, const int constrained, const int add) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_sk) return;
+    const unsigned v = (unsigned)nodes[i];
+    const size_t node = v & ~kClampBit;
+    T acc[3] = {T(0), T(0), T(0)};
+    if (constrained && (v & kClampBit)) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] = x[c * NN + node];
+    } else {
+        const int b = ptr[i], e = ptr[i + 1];
+        for (int k = b; k < e; ++k) {
+            const size_t o = (size_t)idx[k];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[c] += sk[o + (size_t)c * S];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T* yp = y + c * NN + node;
+        *yp = add ? *yp + acc[c] : acc[c];
+    }
+}
+
+template <int P, int Q, typename T, int MAT = kMatElemIso, int GEO = kGeoAffine, bool UNS = false>
 int launch_apply_typed(const ApplyLaunch& L) {
     using C = ApplyCfg<P, Q, T>;
-    if (L.g.NE == 0) return PA_OK;
+    if (L.g.NE == 0 && !UNS) return PA_OK;
     const ApplyTabs<T, P + 1, Q> tab = make_tabs<T, P + 1, Q>(*L.tab);
     const int nb = (L.g.NE + C::E - 1) / C::E;
-    hipLaunchKernelGGL((pa_apply_kernel<P, Q, T, MAT, GEO>), dim3(nb), dim3(C::NT), 0, L.stream, (const T*)L.x,
-                       (T*)L.y, (T*)L.sk, (const T*)L.ed, tab, L.g, L.add, (const T*)L.md, (const T*)L.gd);
-    PA_HIP(hipGetLastError());
+    if (nb > 0) {
+        hipLaunchKernelGGL((pa_apply_kernel<P, Q, T, MAT, GEO, UNS>), dim3(nb), dim3(C::NT), 0, L.stream,
+                           (const T*)L.x, (T*)L.y, (T*)L.sk, (const T*)L.ed, tab, L.g, L.add, (const T*)L.md,
+                           (const T*)L.gd, L.kmap);
+        PA_HIP(hipGetLastError());
+    }
+    if constexpr (UNS) {
+        if (L.n_sk > 0) {
+            hipLaunchKernelGGL((pa_uns_gather_kernel<T>), dim3((L.n_sk + 255) / 256), dim3(256), 0, L.stream,
+                               (const T*)L.x, (T*)L.y, (const T*)L.sk, L.sk_ptr, L.sk_idx, L.sk_node, L.n_sk,
+                               Skel<P + 1>::S, (size_t)L.g.Nn, L.g.clamp != 0 ? 1 : 0, L.add);
+            PA_HIP(hipGetLastError());
+        }
+        return PA_OK;
+    }
     const int nb2 = (L.g.Nn + 255) / 256;
     hipLaunchKernelGGL((pa_skeleton_kernel<P, T>), dim3(nb2), dim3(256), 0, L.stream, (const T*)L.x, (T*)L.y,
                        (const T*)L.sk, L.g, L.add);
@@ -721,8 +792,17 @@ int launch_apply_geometry(const ApplyLaunch& L, int q_off, int dtype) {
     return launch_apply_typed<P, P + 2, float, kMatElemIso, kGeoTri>(L);
 }
 
+// Unstructured meshes (q = p + 2, recomputed trilinear geometry).
+template <int P>
+int launch_apply_unstructured(const ApplyLaunch& L, int q_off, int dtype) {
+    if (q_off != 1) return fail(PA_EUNSUPPORTED, "unstructured meshes are built for q = p + 2 only");
+    if (dtype == PA_F64) return launch_apply_typed<P, P + 2, double, kMatElemIso, kGeoTri, true>(L);
+    return launch_apply_typed<P, P + 2, float, kMatElemIso, kGeoTri, true>(L);
+}
+
 template <int P>
 int launch_apply_p(const ApplyLaunch& L, int q_off, int dtype) {
+    if (L.kmap) return launch_apply_unstructured<P>(L, q_off, dtype);
     if (L.geo != PA_GEOM_AFFINE) return launch_apply_geometry<P>(L, q_off, dtype);
     if (L.mat != PA_MAT_ELEM_ISO) return launch_apply_material<P>(L, q_off, dtype);
     if (dtype == PA_F64) {

@@ -491,6 +491,7 @@ int launch_lin(const ApplyLaunch& L) {
 
 int launch_apply_p1(const ApplyLaunch& L, int q_off, int dtype) {
     // general material data and non-affine geometry go through the sum-factorized kernel
+    if (L.kmap) return launch_apply_unstructured<1>(L, q_off, dtype);
     if (L.geo != PA_GEOM_AFFINE) return launch_apply_geometry<1>(L, q_off, dtype);
     if (L.mat != PA_MAT_ELEM_ISO) return launch_apply_material<1>(L, q_off, dtype);
     if (dtype == PA_F64) {

@@ -63,7 +63,26 @@ __global__ void geometry_qp_kernel(const double* __restrict__ coef, const QRule 
     min_det[e] = mn;
 }
 
-// Map coefficients of every element from the vertex array (host, FP64).
+}  // namespace
+
+// The 21 map coefficients of one element from its corner positions X[a + 2(b + 2c)].
+void element_map_coefficients(const double* const X[8], double* o) {
+    for (int d = 0; d < 3; ++d) {
+        const double x000 = X[0][d], x100 = X[1][d], x010 = X[2][d], x110 = X[3][d];
+        const double x001 = X[4][d], x101 = X[5][d], x011 = X[6][d], x111 = X[7][d];
+        o[d] = x100 - x000;                                                  // a
+        o[3 + d] = x010 - x000;                                              // b
+        o[6 + d] = x001 - x000;                                              // c
+        o[9 + d] = x110 - x100 - x010 + x000;                                // d
+        o[12 + d] = x101 - x100 - x001 + x000;                               // e
+        o[15 + d] = x011 - x010 - x001 + x000;                               // f
+        o[18 + d] = x111 - x110 - x101 - x011 + x100 + x010 + x001 - x000;   // g
+    }
+}
+
+namespace {
+
+// Map coefficients of every element of the box from the vertex array (host, FP64).
 void map_coefficients(const int n[3], const double* v, std::vector<double>& coef) {
     const int64_t NE = (int64_t)n[0] * n[1] * n[2];
     coef.resize((size_t)NE * 21);
@@ -75,18 +94,7 @@ void map_coefficients(const int n[3], const double* v, std::vector<double>& coef
         for (int k = 0; k < 2; ++k)
             for (int j = 0; j < 2; ++j)
                 for (int i = 0; i < 2; ++i) X[i + 2 * (j + 2 * k)] = v + 3 * (b + i * sx + j * sy + k * sz);
-        double* o = coef.data() + (size_t)e * 21;
-        for (int d = 0; d < 3; ++d) {
-            const double x000 = X[0][d], x100 = X[1][d], x010 = X[2][d], x110 = X[3][d];
-            const double x001 = X[4][d], x101 = X[5][d], x011 = X[6][d], x111 = X[7][d];
-            o[d] = x100 - x000;                                                  // a
-            o[3 + d] = x010 - x000;                                              // b
-            o[6 + d] = x001 - x000;                                              // c
-            o[9 + d] = x110 - x100 - x010 + x000;                                // d
-            o[12 + d] = x101 - x100 - x001 + x000;                               // e
-            o[15 + d] = x011 - x010 - x001 + x000;                               // f
-            o[18 + d] = x111 - x110 - x101 - x011 + x100 + x010 + x001 - x000;   // g
-        }
+        element_map_coefficients(X, coef.data() + (size_t)e * 21);
     }
 }
 
@@ -102,13 +110,15 @@ int upload_as(const std::vector<double>& h, void** dst) {
     return PA_OK;
 }
 
-int finish_geometry(pa_op* op, const double* vertices, const double* lam, const double* mu) {
-    const MeshDesc& md = op->mesh;
+}  // namespace
+
+// Device geometry of a non-affine operator from its map coefficients coef [NE][21]:
+// the det J > 0 check at every quadrature point, gd of op->geo's form, and element
+// data holding lambda, mu without det J.
+int finish_geometry(pa_op* op, const std::vector<double>& coef, const double* lam, const double* mu) {
     const int64_t NE = op->NE;
     const int Q = op->q, Q3 = Q * Q * Q;
     const size_t esz = op->dtype == PA_F64 ? sizeof(double) : sizeof(float);
-    std::vector<double> coef;
-    map_coefficients(md.n, vertices, coef);
     double* d_coef = nullptr;
     double* d_min = nullptr;
     int rc = PA_OK;
@@ -173,7 +183,6 @@ int finish_geometry(pa_op* op, const double* vertices, const double* lam, const 
     return rc;
 }
 
-}  // namespace
 }  // namespace pa
 
 using namespace pa;
@@ -198,7 +207,9 @@ extern "C" int pa_elast_setup_geometry(const pa_mesh_t* m, const double* vertice
     rc = create_op(md, p, q, lambda, mu, dtype, (hipStream_t)hip_stream, &op, false);
     if (rc) return rc;
     op->geo = kind;
-    rc = finish_geometry(op, vertices, lambda, mu);
+    std::vector<double> coef;
+    map_coefficients(md.n, vertices, coef);
+    rc = finish_geometry(op, coef, lambda, mu);
     if (rc) {
         pa_elast_destroy(op);
         return rc;

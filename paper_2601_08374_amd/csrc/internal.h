@@ -58,10 +58,16 @@ struct ApplyLaunch {
     void* y;
     void* sk;            // skeleton buffer of the operator (element-boundary contributions)
     const void* ed;      // per-element data of the launch dtype
-    int mat;             // PA_MAT_* form of the material data
-    const void* md;      // per-point Lame parameters or anisotropic stiffness (mat != PA_MAT_ELEM_ISO)
-    int geo;             // PA_GEOM_* form of the element geometry
-    const void* gd;      // per-point J^{-1}, w det J or trilinear coefficients (geo != PA_GEOM_AFFINE)
+    int mat = PA_MAT_ELEM_ISO;   // PA_MAT_* form of the material data
+    const void* md = nullptr;   // per-point Lame parameters or anisotropic stiffness (mat != PA_MAT_ELEM_ISO)
+    int geo = PA_GEOM_AFFINE;   // PA_GEOM_* form of the element geometry
+    const void* gd = nullptr;   // per-point J^{-1}, w det J or trilinear coefficients (geo != PA_GEOM_AFFINE)
+    // unstructured mesh (kmap != nullptr): element-to-node map and skeleton gather lists
+    const int* kmap = nullptr;     // [NE][D^3] global node | kClampBit
+    const int* sk_ptr = nullptr;   // [n_sk + 1] CSR offsets into sk_idx
+    const int* sk_idx = nullptr;   // skeleton word offsets e*3*S + s of component 0
+    const int* sk_node = nullptr;  // [n_sk] global node | kClampBit of every non-interior node
+    int n_sk = 0;
     const Tables* tab;
     int add;             // accumulate into y (y pre-initialised by the caller)
     hipStream_t stream;
@@ -116,6 +122,9 @@ inline int64_t skeleton_words(int p, const int n[3], bool lin_kernel = true) {
 struct AblationBuffers;
 void free_ablation(AblationBuffers* b);
 
+// Clamped-node flag in the element-to-node map of an unstructured mesh.
+constexpr unsigned kClampBit = 0x80000000u;
+
 inline Geom make_geom(const MeshDesc& m, int p, bool constrained) {
     Geom g;
     g.nx = m.n[0]; g.ny = m.n[1]; g.nz = m.n[2];
@@ -146,5 +155,11 @@ struct pa_op {
     void* md = nullptr;              // device material data of dtype (PA_MAT_QP_ISO, PA_MAT_ANISO)
     int geo = PA_GEOM_AFFINE;        // element geometry form
     void* gd = nullptr;              // device geometry data of dtype (PA_GEOM_QP_DATA, PA_GEOM_TRILINEAR)
+    // unstructured mesh (pa_elast_setup_unstructured); kmap == nullptr on the box
+    int* kmap = nullptr;             // device [NE][D^3] global node | kClampBit
+    int* sk_ptr = nullptr;           // device CSR over the non-interior nodes
+    int* sk_idx = nullptr;
+    int* sk_node = nullptr;
+    int n_sk = 0;
     pa_solve_opts_t cached_opts;
 };

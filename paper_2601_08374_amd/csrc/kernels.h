@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "internal.h"
 
 namespace pa {
@@ -24,6 +26,10 @@ int validate_mesh(const pa_mesh_t* m, MeshDesc* out);
 // false sizes the skeleton buffer for the sum-factorized kernel instead.
 int create_op(const MeshDesc& md, int p, int q, const double* lam, const double* mu, int dtype, hipStream_t s,
               pa_op** out, bool lin_kernel = true);
+// geometry.hip
+void element_map_coefficients(const double* const X[8], double* o);
+int finish_geometry(pa_op* op, const std::vector<double>& coef, const double* lam, const double* mu);
+
 int launch_rhs(const pa_op* op, const double f[3], int face, const double t[3], double* b, const double* d_vert);
 
 // vec.hip

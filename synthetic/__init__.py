@@ -302,44 +302,64 @@ class HexMesh:
 
 
 def box_as_unstructured(mesh: BoxMesh, verts: np.ndarray, p: int, seed: int = 3, permute: bool = True,
-                        reorient: bool = True):
+                        reorient: bool = True, renumber: bool = True, shuffle_nodes: bool = False):
     """The box mesh with vertex positions verts ([(n0+1)(n1+1)(n2+1), 3], see
-    perturbed_vertices) written as an unstructured mesh: elements in a random order,
-    each in a random one of the 24 orientations of the cube, nodes renumbered by
-    hex_high_order_nodes.  Returns (HexMesh, node_map) with node_map[u] = box node of
-    unstructured node u (box node gx + Nx (gy + Ny gz)); clamped nodes follow the box's
-    clamped faces."""
+    perturbed_vertices) written as an unstructured mesh: elements in a random order
+    (permute), each in a random one of the 24 orientations of the cube (reorient), nodes
+    numbered by hex_high_order_nodes (renumber; small meshes) or kept in box order,
+    optionally relabelled by a random permutation (shuffle_nodes).  Returns (HexMesh,
+    node_map, elem_order): node_map[u] = box node (gx + Nx (gy + Ny gz)) of node u and
+    elem_order[i] = box element of element i; clamped nodes follow the box's faces."""
     rng = np.random.default_rng(seed)
     n0, n1, n2 = mesh.n
     D = p + 1
     NE = n0 * n1 * n2
+    Nx, Ny, Nz = n0 * p + 1, n1 * p + 1, n2 * p + 1
     ez, ey, ex = np.meshgrid(np.arange(n2), np.arange(n1), np.arange(n0), indexing="ij")
     ex, ey, ez = ex.ravel(), ey.ravel(), ez.ravel()
-    order = rng.permutation(NE) if permute else np.arange(NE)
-    rots = _cube_rotations()
-    Nx, Ny = n0 * p + 1, n1 * p + 1
-    ev = np.empty((NE, 8), dtype=np.int64)
-    box_nodes = np.empty((NE, D ** 3), dtype=np.int64)
+    # box numbering of every element's local nodes and vertices
     kz, ky, kx = np.meshgrid(np.arange(D), np.arange(D), np.arange(D), indexing="ij")
-    new_idx = np.stack([kx.ravel(), ky.ravel(), kz.ravel()], axis=1)     # new local coordinates
+    loc = np.stack([kx.ravel(), ky.ravel(), kz.ravel()], axis=1)
     cz, cy, cx = np.meshgrid(np.arange(2), np.arange(2), np.arange(2), indexing="ij")
-    new_c = np.stack([cx.ravel(), cy.ravel(), cz.ravel()], axis=1)
-    for i, e in enumerate(order):
-        perm, flip = rots[rng.integers(len(rots))] if reorient else ((0, 1, 2), (0, 0, 0))
-        old = np.empty_like(new_idx)
-        oc = np.empty_like(new_c)
+    cor = np.stack([cx.ravel(), cy.ravel(), cz.ravel()], axis=1)
+    # per rotation: the old local node / corner seen at each new local node / corner
+    rots = _cube_rotations()
+    PI = np.empty((len(rots), D ** 3), dtype=np.int64)
+    PV = np.empty((len(rots), 8), dtype=np.int64)
+    for r, (perm, flip) in enumerate(rots):
+        old = np.empty_like(loc)
+        oc = np.empty_like(cor)
         for k in range(3):
-            old[:, perm[k]] = np.where(flip[k], p - new_idx[:, k], new_idx[:, k])
-            oc[:, perm[k]] = np.where(flip[k], 1 - new_c[:, k], new_c[:, k])
-        gx, gy, gz = ex[e] * p + old[:, 0], ey[e] * p + old[:, 1], ez[e] * p + old[:, 2]
-        box_nodes[i] = gx + Nx * (gy + Ny * gz)
-        vx, vy, vz = ex[e] + oc[:, 0], ey[e] + oc[:, 1], ez[e] + oc[:, 2]
-        ev[i] = vx + (n0 + 1) * (vy + (n1 + 1) * vz)
-    en, nn = hex_high_order_nodes(ev, p, num_vertices=(n0 + 1) * (n1 + 1) * (n2 + 1))
-    node_map = np.full(nn, -1, dtype=np.int64)
-    node_map[en.ravel()] = box_nodes.ravel()
-    # clamped box faces, carried to the unstructured numbering
-    Nz = n2 * p + 1
+            old[:, perm[k]] = np.where(flip[k], p - loc[:, k], loc[:, k])
+            oc[:, perm[k]] = np.where(flip[k], 1 - cor[:, k], cor[:, k])
+        PI[r] = old[:, 0] + D * (old[:, 1] + D * old[:, 2])
+        PV[r] = oc[:, 0] + 2 * (oc[:, 1] + 2 * oc[:, 2])
+    ident = rots.index(((0, 1, 2), (0, 0, 0)))
+    order = rng.permutation(NE) if permute else np.arange(NE)
+    r_e = rng.integers(len(rots), size=NE) if reorient else np.full(NE, ident)
+    gx = (ex[order] * p)[:, None] + loc[None, :, 0]
+    gy = (ey[order] * p)[:, None] + loc[None, :, 1]
+    gz = (ez[order] * p)[:, None] + loc[None, :, 2]
+    box_nodes = gx + Nx * (gy + Ny * gz)                                   # [NE, D^3] in old local order
+    box_nodes = np.take_along_axis(box_nodes, PI[r_e], axis=1)
+    vx = ex[order][:, None] + cor[None, :, 0]
+    vy = ey[order][:, None] + cor[None, :, 1]
+    vz = ez[order][:, None] + cor[None, :, 2]
+    ev = vx + (n0 + 1) * (vy + (n1 + 1) * vz)
+    ev = np.take_along_axis(ev, PV[r_e], axis=1)
+    if renumber:
+        en, nn = hex_high_order_nodes(ev, p, num_vertices=(n0 + 1) * (n1 + 1) * (n2 + 1))
+        node_map = np.full(nn, -1, dtype=np.int64)
+        node_map[en.ravel()] = box_nodes.ravel()
+    else:
+        nn = Nx * Ny * Nz
+        if shuffle_nodes:
+            new_id = rng.permutation(nn)
+            en = new_id[box_nodes].astype(np.int32)
+            node_map = np.argsort(new_id)
+        else:
+            en = box_nodes.astype(np.int32)
+            node_map = np.arange(nn)
     g = np.arange(Nx * Ny * Nz)
     gx, gy, gz = g % Nx, (g // Nx) % Ny, g // (Nx * Ny)
     f = mesh.clamped_faces
@@ -347,7 +367,7 @@ def box_as_unstructured(mesh: BoxMesh, verts: np.ndarray, p: int, seed: int = 3,
          (((f & 8) > 0) & (gy == Ny - 1)) | (((f & 16) > 0) & (gz == 0)) | (((f & 32) > 0) & (gz == Nz - 1))
     hm = HexMesh(vertices=np.asarray(verts, dtype=np.float64), elem_vertices=ev.astype(np.int32), p=p,
                  elem_nodes=en, num_nodes=nn, clamped=cl[node_map])
-    return hm, node_map
+    return hm, node_map, order
 
 
 def ogrid_cylinder(p: int, n: int = 4, m: int = 3, nz: int = 4, R: float = 1.0, a: float = 0.4,

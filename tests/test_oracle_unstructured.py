@@ -59,7 +59,10 @@ def _boundary_nodes(hm):
 def test_numbering_conforming(p):
     for hm in (syn.ogrid_cylinder(p, seed=1),
                syn.box_as_unstructured(syn.BoxMesh(n=(3, 2, 2)),
-                                       syn.perturbed_vertices(syn.BoxMesh(n=(3, 2, 2)), 0.2, 1), p)[0]):
+                                       syn.perturbed_vertices(syn.BoxMesh(n=(3, 2, 2)), 0.2, 1), p)[0],
+               syn.box_as_unstructured(syn.BoxMesh(n=(3, 2, 2)),
+                                       syn.perturbed_vertices(syn.BoxMesh(n=(3, 2, 2)), 0.2, 1), p,
+                                       renumber=False, shuffle_nodes=True)[0]):
         _, spread = _node_coords(hm)
         assert spread <= 1e-14
         counts = np.bincount(hm.elem_nodes.ravel(), minlength=hm.num_nodes)
@@ -79,13 +82,7 @@ def test_box_as_unstructured_matches_box(p):
     lam, mu = rng.uniform(0.5, 2.0, NE), rng.uniform(0.5, 2.0, NE)
     for amp in (0.0, 0.2):
         verts = syn.perturbed_vertices(mesh, amp=amp, seed=p, interior_only=False)
-        hm, node_map = syn.box_as_unstructured(mesh, verts, p, seed=p)
-        order = np.empty(NE, dtype=np.int64)
-        # the generator's element order: recover it from the first vertex set of each element
-        box_ev = geometry.element_vertices(mesh, verts)
-        keys = {tuple(sorted(map(tuple, np.round(box_ev[e], 12)))): e for e in range(NE)}
-        for i in range(NE):
-            order[i] = keys[tuple(sorted(map(tuple, np.round(hm.vertices[hm.elem_vertices[i]], 12))))]
+        hm, node_map, order = syn.box_as_unstructured(mesh, verts, p, seed=p)
         ref_op = (elasticity.Operator(mesh, p, p + 2, lam, mu) if amp == 0.0 else
                   geometry.TrilinearOperator(mesh, p, p + 2, verts, lam, mu))
         un = geometry.UnstructuredOperator(hm, p + 2, lam[order], mu[order])
@@ -96,6 +93,13 @@ def test_box_as_unstructured_matches_box(p):
             yb = ref_op.apply(xb, constrained=constrained)
             yu = un.apply(xb[idx], constrained=constrained)
             assert np.linalg.norm(yu - yb[idx]) <= 1e-12 * np.linalg.norm(yb)
+        # box numbering kept, nodes relabelled at random
+        hm2, node_map2, order2 = syn.box_as_unstructured(mesh, verts, p, seed=p + 7, renumber=False,
+                                                         shuffle_nodes=True)
+        idx2 = np.concatenate([node_map2 + c * Nb for c in range(3)])
+        yu2 = geometry.UnstructuredOperator(hm2, p + 2, lam[order2], mu[order2]).apply(xb[idx2], constrained=True)
+        yb2 = ref_op.apply(xb, constrained=True)
+        assert np.linalg.norm(yu2 - yb2[idx2]) <= 1e-12 * np.linalg.norm(yb2)
 
 
 def _polygon_volume(n, R, H):
