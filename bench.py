@@ -52,17 +52,7 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def flops_per_element(p: int, q: int | None = None) -> int:
-    """Per-element FLOPs of the optimized operator, the paper's count (Sec. 5.3.1 table):
-    30 D^3 Q + 36 D^2 Q^2 + 36 D Q^3 + 113 Q^3 + 12 D^3, D = p+1, Q = p+2."""
-    D = p + 1
-    Q = p + 2 if q is None else q
-    return 30 * D ** 3 * Q + 36 * D ** 2 * Q ** 2 + 36 * D * Q ** 3 + 113 * Q ** 3 + 12 * D ** 3
-
-
-def algorithmic_bytes(N: int, NE: int, word: int) -> int:
-    """Read x once, write y once, 12 words of per-element PA data."""
-    return 2 * word * N + 12 * word * NE
+from paper_2601_08374_amd.benchmarks import algorithmic_bytes, flops_per_element  # noqa: E402
 
 
 KERNEL_SOURCES = ("internal.h", "apply_kernel.h", "apply_p1.hip")
@@ -141,8 +131,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU sharding is described in "
-                                   "DESIGN.md but not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "single-GPU implementation: --gpus must be 1 (the partition of the mesh "
+                                   "over several GPUs is not implemented)", "n_gpus": args.gpus}))
         return 2
 
     import numpy as np

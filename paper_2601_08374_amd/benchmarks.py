@@ -68,16 +68,100 @@ def cantilever_solves(torch, dev, ps=(4, 6, 8)):
     return out
 
 
-def apply_material(torch, dev, ps=(1, 2, 4, 8), reps=10):
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X vector FP64 / FP32
+PEAK_HBM_GBS = 8000.0                        # MI355X HBM3E
+
+# Pointwise FLOPs per quadrature point beyond the isotropic stress of the paper's count:
+# per-point Lame data (2 products), the anisotropic C eps_V (6 strains, 36 products + 30
+# sums, 6 scalings, less the ~15 of the isotropic stress), the recomputed trilinear
+# Jacobian (2 x 3 column FMAs, 9 cofactors of 3, det J of 5, 1/det J and its scaling).
+EXTRA_POINT_FLOPS = {"qpoint_iso": 2, "anisotropic": 60, "trilinear": 46}
+
+
+def flops_per_element(p: int, q: int | None = None) -> int:
+    """Per-element FLOPs of the optimized operator, the paper's count (Sec. 5.3.1 table):
+    30 D^3 Q + 36 D^2 Q^2 + 36 D Q^3 + 113 Q^3 + 12 D^3, D = p+1, Q = p+2."""
+    D = p + 1
+    Q = p + 2 if q is None else q
+    return 30 * D ** 3 * Q + 36 * D ** 2 * Q ** 2 + 36 * D * Q ** 3 + 113 * Q ** 3 + 12 * D ** 3
+
+
+def algorithmic_bytes(N: int, NE: int, word: int) -> int:
+    """Read x once, write y once, 12 words of per-element PA data."""
+    return 2 * word * N + 12 * word * NE
+
+
+def _rates(N, NE, p, word, dname, t, extra_words=0, extra_bytes=0, extra_flops_pt=0):
+    """Time per apply and its rates against the FP VALU and HBM peaks.  Algorithmic bytes:
+    x and y once, the 12-word element data, the form's extra words per element and extra
+    bytes; FLOPs: the paper's count plus the form's extra pointwise FLOPs."""
+    Q = p + 2
+    fl = (flops_per_element(p) + extra_flops_pt * Q ** 3) * NE
+    by = algorithmic_bytes(N, NE, word) + extra_words * word * NE + extra_bytes
+    return {"us": round(t * 1e6, 1), "gdofs": round(N / t / 1e9, 3), "tflops": round(fl / t / 1e12, 3),
+            "frac_alu": round(fl / t / 1e12 / PEAK_TFLOPS[dname], 4), "gbs": round(by / t / 1e9, 1),
+            "frac_hbm": round(by / t / 1e9 / PEAK_HBM_GBS, 4), "algorithmic_bytes": int(by),
+            "flops": int(fl)}
+
+
+def _time_apply(torch, dev, op, reps):
+    """Mean HIP-event time of reps applies (after one warm-up) on the current stream."""
+    import synthetic as syn
+    tdt = torch.float64 if op.dtype == 0 else torch.float32
+    x = torch.tensor(syn.uniform_vector(op.N, 0), dtype=tdt, device=dev)
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    op.apply(x, y)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        op.apply(x, y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / reps
+
+
+def _sub_box(mesh, f=4):
+    """The first 1/f^3 of a box (n // f per axis) with the same element size: the bounded
+    sample the CPU oracle is timed on."""
+    import synthetic as syn
+    n = tuple(max(1, k // f) for k in mesh.n)
+    L = tuple(mesh.L[a] * n[a] / mesh.n[a] for a in range(3))
+    return syn.BoxMesh(n=n, L=L, A=mesh.A, x0=mesh.x0)
+
+
+def _oracle_rate(build, N):
+    """GDoF/s of one FP64 oracle apply (setup excluded) of a sample with N dofs."""
+    import synthetic as syn
+    op = build()
+    x = syn.uniform_vector(N, 0)
+    t0 = time.perf_counter()
+    op.apply(x)
+    t = time.perf_counter() - t0
+    return {"gdofs": N / t / 1e9, "t_apply_s": round(t, 4), "N": N}
+
+
+def _cpu_note(section):
+    import os
+    return {"kind": "oracle", "cores": len(os.sched_getaffinity(0)), "unit": "GDoF/s",
+            "sample": f"one FP64 {section} oracle apply at each p on the first 1/64 of the sheared box "
+                      "(n // 4 elements per axis, same element size), setup excluded"}
+
+
+def apply_material(torch, dev, ps=(1, 2, 4, 8), reps=10, oracle=True):
     """The fused apply with the three material data forms on the sheared box (q = p+2):
     per-element Lame parameters, per-quadrature-point Lame parameters and a per-element
-    anisotropic Voigt stiffness; HIP-event time per apply, FP64 and FP32."""
+    anisotropic Voigt stiffness; HIP-event time per apply, FP64 and FP32, with rates
+    against the VALU and HBM peaks, and the FP64 oracle timed on the host cores."""
     import synthetic as syn
     import paper_2601_08374_amd as pa
+    from oracle import material
     out = {"workload": "sheared box (~4.2M dofs), q=p+2; two materials (element), +-30% per point "
                        f"(quadrature point), random SPD Voigt stiffness (anisotropic); mean of {reps} "
-                       "applies after one warm-up, HIP events"}
-    stream = torch.cuda.current_stream()
+                       "applies after one warm-up, HIP events",
+           "extra_point_flops": {k: v for k, v in EXTRA_POINT_FLOPS.items() if k != "trilinear"}}
+    cpu = _cpu_note("material (strain-displacement form)")
     for p in ps:
         mesh = syn.sheared_box_mesh(p)
         NE, q = mesh.num_elements, p + 2
@@ -89,122 +173,129 @@ def apply_material(torch, dev, ps=(1, 2, 4, 8), reps=10):
         c21 = np.ascontiguousarray(C[:, np.triu_indices(6)[0], np.triu_indices(6)[1]])
         rec = {}
         for dtype, dname in ((pa.PA_F64, "f64"), (pa.PA_F32, "f32")):
-            tdt = torch.float64 if dtype == pa.PA_F64 else torch.float32
-            for form, make in (("element_iso", lambda: pa.Operator(mesh, p, lam, mu, dtype=dtype)),
-                               ("qpoint_iso", lambda: pa.Operator.with_material(mesh, p, pa.PA_MAT_QP_ISO, qp,
-                                                                                dtype=dtype)),
-                               ("anisotropic", lambda: pa.Operator.with_material(mesh, p, pa.PA_MAT_ANISO, c21,
-                                                                                 dtype=dtype))):
+            word = 8 if dtype == pa.PA_F64 else 4
+            forms = (("element_iso", lambda: pa.Operator(mesh, p, lam, mu, dtype=dtype), 0, 0),
+                     ("qpoint_iso", lambda: pa.Operator.with_material(mesh, p, pa.PA_MAT_QP_ISO, qp, dtype=dtype),
+                      2 * q ** 3, EXTRA_POINT_FLOPS["qpoint_iso"]),
+                     ("anisotropic", lambda: pa.Operator.with_material(mesh, p, pa.PA_MAT_ANISO, c21, dtype=dtype),
+                      21, EXTRA_POINT_FLOPS["anisotropic"]))
+            for form, make, xw, xf in forms:
                 op = make()
-                x = torch.tensor(syn.uniform_vector(op.N, 0), dtype=tdt, device=dev)
-                y = torch.empty_like(x)
-                op.apply(x, y)
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                for _ in range(reps):
-                    op.apply(x, y)
-                e1.record(stream)
-                torch.cuda.synchronize()
-                t = e0.elapsed_time(e1) * 1e-3 / reps
-                rec[f"{form}_{dname}"] = {"us": round(t * 1e6, 1), "gdofs": round(op.N / t / 1e9, 3)}
+                t = _time_apply(torch, dev, op, reps)
+                rec[f"{form}_{dname}"] = _rates(op.N, NE, p, word, dname, t, extra_words=xw, extra_flops_pt=xf)
                 op.close()
-                del x, y
         out[f"p{p}"] = rec
+        if oracle:
+            sub = _sub_box(mesh)
+            ns = sub.num_elements
+            Cs = material.isotropic_voigt(*syn.quadrature_point_lame(lam[:ns], mu[:ns], q, seed=4))
+            cpu[f"p{p}"] = {"qpoint_iso": _oracle_rate(lambda: material.GeneralOperator(sub, p, q, Cs),
+                                                       sub.num_dofs(p)),
+                            "anisotropic": _oracle_rate(lambda: material.GeneralOperator(sub, p, q, C[:ns]),
+                                                        sub.num_dofs(p))}
+            del Cs
         del qp, C, c21
         torch.cuda.empty_cache()
+    if oracle:
+        out["cpu_oracle"] = cpu
     return out
 
 
-def apply_geometry(torch, dev, ps=(1, 2, 4, 8), reps=10):
+def apply_geometry(torch, dev, ps=(1, 2, 4, 8), reps=10, oracle=True):
     """The fused apply on the sheared box with its interior vertices moved (trilinear
     hexahedra): geometry stored per quadrature point (J^{-1}, w det J) vs recomputed per
     point from 21 map coefficients per element, next to the affine box; HIP-event time
-    per apply, FP64 and FP32."""
+    per apply, FP64 and FP32, rates against the peaks, and the FP64 oracle on the host."""
     import synthetic as syn
     import paper_2601_08374_amd as pa
+    from oracle import geometry
     out = {"workload": "sheared box (~4.2M dofs), q=p+2, two materials; interior vertices moved by up to "
-                       f"0.2 of the spacing (seed 17); mean of {reps} applies after one warm-up, HIP events"}
-    stream = torch.cuda.current_stream()
+                       f"0.2 of the spacing (seed 17); mean of {reps} applies after one warm-up, HIP events",
+           "extra_point_flops": {"trilinear": EXTRA_POINT_FLOPS["trilinear"]}}
+    cpu = _cpu_note("trilinear-geometry (quadrature sum with per-point Jacobians)")
     for p in ps:
         mesh = syn.sheared_box_mesh(p)
-        lam, mu = syn.two_material_lame(mesh.num_elements, seed=1)
+        NE, q = mesh.num_elements, p + 2
+        lam, mu = syn.two_material_lame(NE, seed=1)
         verts = syn.perturbed_vertices(mesh, amp=0.2, seed=17)
         rec = {}
         for dtype, dname in ((pa.PA_F64, "f64"), (pa.PA_F32, "f32")):
-            tdt = torch.float64 if dtype == pa.PA_F64 else torch.float32
-            for form, make in (("affine", lambda: pa.Operator(mesh, p, lam, mu, dtype=dtype)),
-                               ("qp_data", lambda: pa.Operator.with_geometry(mesh, p, verts, lam, mu,
-                                                                             kind=pa.PA_GEOM_QP_DATA, dtype=dtype)),
-                               ("trilinear", lambda: pa.Operator.with_geometry(mesh, p, verts, lam, mu,
-                                                                               kind=pa.PA_GEOM_TRILINEAR,
-                                                                               dtype=dtype))):
+            word = 8 if dtype == pa.PA_F64 else 4
+            forms = (("affine", lambda: pa.Operator(mesh, p, lam, mu, dtype=dtype), 0, 0),
+                     ("qp_data", lambda: pa.Operator.with_geometry(mesh, p, verts, lam, mu,
+                                                                   kind=pa.PA_GEOM_QP_DATA, dtype=dtype),
+                      10 * q ** 3, 0),
+                     ("trilinear", lambda: pa.Operator.with_geometry(mesh, p, verts, lam, mu,
+                                                                     kind=pa.PA_GEOM_TRILINEAR, dtype=dtype),
+                      21, EXTRA_POINT_FLOPS["trilinear"]))
+            for form, make, xw, xf in forms:
                 op = make()
-                x = torch.tensor(syn.uniform_vector(op.N, 0), dtype=tdt, device=dev)
-                y = torch.empty_like(x)
-                op.apply(x, y)
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                for _ in range(reps):
-                    op.apply(x, y)
-                e1.record(stream)
-                torch.cuda.synchronize()
-                t = e0.elapsed_time(e1) * 1e-3 / reps
-                rec[f"{form}_{dname}"] = {"us": round(t * 1e6, 1), "gdofs": round(op.N / t / 1e9, 3)}
+                t = _time_apply(torch, dev, op, reps)
+                rec[f"{form}_{dname}"] = _rates(op.N, NE, p, word, dname, t, extra_words=xw, extra_flops_pt=xf)
                 op.close()
-                del x, y
         out[f"p{p}"] = rec
+        if oracle:
+            sub = _sub_box(mesh)
+            sv = syn.perturbed_vertices(sub, amp=0.2, seed=17)
+            ns = sub.num_elements
+            cpu[f"p{p}"] = _oracle_rate(lambda: geometry.TrilinearOperator(sub, p, q, sv, lam[:ns], mu[:ns]),
+                                        sub.num_dofs(p))
         torch.cuda.empty_cache()
+    if oracle:
+        out["cpu_oracle"] = cpu
     return out
 
 
-def apply_unstructured(torch, dev, ps=(1, 2, 4, 8), reps=10):
+def apply_unstructured(torch, dev, ps=(1, 2, 4, 8), reps=10, oracle=True):
     """The fused apply on the distorted sheared box given as an unstructured mesh
     (explicit element-to-node map, every element in a random orientation), in box order
     and with elements and nodes shuffled at random (no locality), next to the structured
-    trilinear operator on the same geometry; HIP-event time per apply."""
+    trilinear operator on the same geometry; HIP-event time per apply, rates against the
+    peaks (algorithmic bytes add the map, 4 (p+1)^3 bytes per element), and the FP64
+    oracle on the host."""
     import synthetic as syn
     import paper_2601_08374_amd as pa
+    from oracle import geometry
     out = {"workload": "sheared box (~4.2M dofs), q=p+2, two materials, interior vertices moved by up to 0.2 "
                        "of the spacing; unstructured: random orientation per element, box order ('ordered') or "
                        f"random element and node order ('shuffled'); mean of {reps} applies after one warm-up"}
-    stream = torch.cuda.current_stream()
-
-    def timed(op, tdt):
-        x = torch.tensor(syn.uniform_vector(op.N, 0), dtype=tdt, device=dev)
-        y = torch.empty_like(x)
-        op.apply(x, y)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            op.apply(x, y)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        t = e0.elapsed_time(e1) * 1e-3 / reps
-        op.close()
-        return {"us": round(t * 1e6, 1), "gdofs": round(op.N / t / 1e9, 3)}
-
+    cpu = _cpu_note("unstructured-mesh (quadrature sum, explicit map)")
     for p in ps:
         mesh = syn.sheared_box_mesh(p)
-        lam, mu = syn.two_material_lame(mesh.num_elements, seed=1)
+        NE = mesh.num_elements
+        lam, mu = syn.two_material_lame(NE, seed=1)
         verts = syn.perturbed_vertices(mesh, amp=0.2, seed=17)
         rec = {}
         hm, _, order = syn.box_as_unstructured(mesh, verts, p, seed=1, permute=False, renumber=False)
         hs, _, order_s = syn.box_as_unstructured(mesh, verts, p, seed=2, permute=True, renumber=False,
                                                  shuffle_nodes=True)
+        mapb = 4 * (p + 1) ** 3 * NE
         for dtype, dname in ((pa.PA_F64, "f64"), (pa.PA_F32, "f32")):
-            tdt = torch.float64 if dtype == pa.PA_F64 else torch.float32
-            rec[f"structured_trilinear_{dname}"] = timed(
-                pa.Operator.with_geometry(mesh, p, verts, lam, mu, kind=pa.PA_GEOM_TRILINEAR, dtype=dtype), tdt)
-            rec[f"unstructured_ordered_{dname}"] = timed(
-                pa.Operator.unstructured(hm, lam[order], mu[order], dtype=dtype), tdt)
-            rec[f"unstructured_shuffled_{dname}"] = timed(
-                pa.Operator.unstructured(hs, lam[order_s], mu[order_s], dtype=dtype), tdt)
+            word = 8 if dtype == pa.PA_F64 else 4
+            xf = EXTRA_POINT_FLOPS["trilinear"]
+            forms = (("structured_trilinear", lambda: pa.Operator.with_geometry(
+                          mesh, p, verts, lam, mu, kind=pa.PA_GEOM_TRILINEAR, dtype=dtype), 0),
+                     ("unstructured_ordered", lambda: pa.Operator.unstructured(hm, lam[order], mu[order],
+                                                                               dtype=dtype), mapb),
+                     ("unstructured_shuffled", lambda: pa.Operator.unstructured(hs, lam[order_s], mu[order_s],
+                                                                                dtype=dtype), mapb))
+            for form, make, xb in forms:
+                op = make()
+                t = _time_apply(torch, dev, op, reps)
+                rec[f"{form}_{dname}"] = _rates(op.N, NE, p, word, dname, t, extra_words=21, extra_bytes=xb,
+                                                extra_flops_pt=xf)
+                op.close()
         out[f"p{p}"] = rec
         del hm, hs
+        if oracle:
+            sub = _sub_box(mesh)
+            sv = syn.perturbed_vertices(sub, amp=0.2, seed=17)
+            hsub, _, osub = syn.box_as_unstructured(sub, sv, p, seed=1, permute=False, renumber=False)
+            cpu[f"p{p}"] = _oracle_rate(lambda: geometry.UnstructuredOperator(hsub, p + 2, lam[osub], mu[osub]),
+                                        hsub.num_dofs)
         torch.cuda.empty_cache()
+    if oracle:
+        out["cpu_oracle"] = cpu
     return out
 
 
