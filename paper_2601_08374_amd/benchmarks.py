@@ -302,7 +302,8 @@ def apply_unstructured(torch, dev, ps=(1, 2, 4, 8), reps=10, oracle=True):
 def apply_ablation(torch, dev, ps=(1, 2, 4, 8), reps=5):
     """Cumulative ablation of the apply on the sheared box (FP64, q = p+2), in the order of the
     paper's ablation table: unfused dense baseline -> + sum factorization -> + Voigt stress ->
-    + fusion into one kernel (the production apply).  HIP-event time per apply."""
+    + fusion into one kernel (the production apply).  HIP-event time per apply, with rates
+    against the FP64 VALU and HBM peaks on the fused operator's FLOP and byte counts."""
     import synthetic as syn
     import paper_2601_08374_amd as pa
     names = [("unfused_dense", pa.capi.PA_VARIANT_UNFUSED_DENSE), ("unfused_sf", pa.capi.PA_VARIANT_UNFUSED_SF),
@@ -327,7 +328,9 @@ def apply_ablation(torch, dev, ps=(1, 2, 4, 8), reps=5):
             e1.record(stream)
             torch.cuda.synchronize()
             t = e0.elapsed_time(e1) * 1e-3 / reps
-            r = {"us": round(t * 1e6, 1), "gdofs": round(op.N / t / 1e9, 3)}
+            # rates on the fused operator's algorithmic FLOPs and bytes (the dense variant
+            # executes O(p^6) FLOPs per element, the unfused ones move QVec arrays besides)
+            r = _rates(op.N, mesh.num_elements, p, 8, "f64", t)
             if prev is not None:
                 r["marginal_speedup"] = round(prev / t, 2)
             rec[name] = r
