@@ -171,7 +171,7 @@ int apply_op(const pa_op* op, const void* x, void* y, int flags) {
         L.g = g;
         L.kmap = op->kmap;
         L.sk_ptr = op->sk_ptr;
-        L.sk_idx = op->sk_idx;
+        L.kpos = op->kpos;
         L.sk_node = op->sk_node;
         L.n_sk = op->n_sk;
     } else {
@@ -295,7 +295,7 @@ void pa_elast_destroy(pa_op_t* op) {
     if (op->ed) (void)hipFree(op->ed);
     if (op->md) (void)hipFree(op->md);
     if (op->gd) (void)hipFree(op->gd);
-    for (int* a : {op->kmap, op->sk_ptr, op->sk_idx, op->sk_node})
+    for (int* a : {op->kmap, op->sk_ptr, op->kpos, op->sk_node})
         if (a) (void)hipFree(a);
     if (op->sk) (void)hipFree(op->sk);
     if (op->d_tab) (void)hipFree(op->d_tab);

@@ -296,13 +296,14 @@ enum : int { kGeoAffine = 0, kGeoQp = 1, kGeoTri = 2 };
 
 // UNS: unstructured mesh.  Nodes come from the element-to-node map kmap (global node,
 // kClampBit on clamped nodes; g.clamp != 0 for a constrained apply), element-interior
-// nodes go to y directly and element-boundary nodes to the element-major skeleton
-// buffer, which pa_uns_gather_kernel sums per node.
+// nodes go to y directly and element-boundary nodes to the skeleton entry kpos of
+// their (element, slot): entries are stored in the order of the per-node gather lists,
+// so pa_uns_gather_kernel reads each node's contributions as one contiguous run.
 template <int P, int Q, typename T, int MAT = kMatElemIso, int GEO = kGeoAffine, bool UNS = false>
 __global__ void __launch_bounds__((ApplyCfg<P, Q, T>::NT))
 pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, const T* __restrict__ ed,
                 const ApplyTabs<T, P + 1, Q> tab, const Geom g, const int add, const T* __restrict__ md,
-                const T* __restrict__ gd, const int* __restrict__ kmap) {
+                const T* __restrict__ gd, const int* __restrict__ kmap, const int* __restrict__ kpos) {
     static_assert(GEO == kGeoAffine || MAT == kMatElemIso, "non-affine geometry takes per-element Lame data");
     static_assert(!UNS || GEO == kGeoTri, "unstructured meshes take the recomputed trilinear geometry");
     using C = ApplyCfg<P, Q, T>;
@@ -636,7 +637,7 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
                             const T v = ((ln_cl >> (j * D + ix)) & 1u) ? x[o] : yo[ix];
                             y[o] = add ? y[o] + v : v;
                         } else {
-                            sk[((size_t)(e0 + el) * 3 + c) * SK::S + SK::index(ix, iy, iz)] = yo[ix];
+                            sk[(size_t)kpos[(size_t)(e0 + el) * SK::S + SK::index(ix, iy, iz)] * 3 + c] = yo[ix];
                         }
                     } else if (SK::interior(ix, iy, iz)) {
                         T* yp = y + c * NN + ln_node[j] + ix;
@@ -708,14 +709,14 @@ pa_skeleton_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __restri
     }
 }
 
-// Unstructured mesh: every non-interior node i sums its skeleton entries in the fixed
-// order of its list (element, then slot ascending) and writes y; a clamped node keeps
-// its input in a constrained apply, a node of no element gets 0.
+// Unstructured mesh: every non-interior node i sums its skeleton entries [ptr[i],
+// ptr[i+1]) (its elements in ascending order) and writes y; a clamped node keeps its
+// input in a constrained apply, a node of no element gets 0.
 template <typename T>
 __global__ void __launch_bounds__(256)
 pa_uns_gather_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ sk,
-                     const int* __restrict__ ptr, const int* __restrict__ idx, const int* __restrict__ nodes,
-                     const int n_sk, const int S, const size_t NN, const int constrained, const int add) {
+                     const int* __restrict__ ptr, const int* __restrict__ nodes, const int n_sk, const size_t NN,
+                     const int constrained, const int add) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_sk) return;
     const unsigned v = (unsigned)nodes[i];
@@ -727,9 +728,8 @@ pa_uns_gather_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __rest
     } else {
         const int b = ptr[i], e = ptr[i + 1];
         for (int k = b; k < e; ++k) {
-            const size_t o = (size_t)idx[k];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) acc[c] += sk[o + (size_t)c * S];
+            for (int c = 0; c < 3; ++c) acc[c] += sk[(size_t)k * 3 + c];
         }
     }
 #pragma unroll
@@ -748,14 +748,14 @@ int launch_apply_typed(const ApplyLaunch& L) {
     if (nb > 0) {
         hipLaunchKernelGGL((pa_apply_kernel<P, Q, T, MAT, GEO, UNS>), dim3(nb), dim3(C::NT), 0, L.stream,
                            (const T*)L.x, (T*)L.y, (T*)L.sk, (const T*)L.ed, tab, L.g, L.add, (const T*)L.md,
-                           (const T*)L.gd, L.kmap);
+                           (const T*)L.gd, L.kmap, L.kpos);
         PA_HIP(hipGetLastError());
     }
     if constexpr (UNS) {
         if (L.n_sk > 0) {
             hipLaunchKernelGGL((pa_uns_gather_kernel<T>), dim3((L.n_sk + 255) / 256), dim3(256), 0, L.stream,
-                               (const T*)L.x, (T*)L.y, (const T*)L.sk, L.sk_ptr, L.sk_idx, L.sk_node, L.n_sk,
-                               Skel<P + 1>::S, (size_t)L.g.Nn, L.g.clamp != 0 ? 1 : 0, L.add);
+                               (const T*)L.x, (T*)L.y, (const T*)L.sk, L.sk_ptr, L.sk_node, L.n_sk,
+                               (size_t)L.g.Nn, L.g.clamp != 0 ? 1 : 0, L.add);
             PA_HIP(hipGetLastError());
         }
         return PA_OK;

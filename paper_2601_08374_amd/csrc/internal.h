@@ -64,8 +64,8 @@ struct ApplyLaunch {
     const void* gd = nullptr;   // per-point J^{-1}, w det J or trilinear coefficients (geo != PA_GEOM_AFFINE)
     // unstructured mesh (kmap != nullptr): element-to-node map and skeleton gather lists
     const int* kmap = nullptr;     // [NE][D^3] global node | kClampBit
-    const int* sk_ptr = nullptr;   // [n_sk + 1] CSR offsets into sk_idx
-    const int* sk_idx = nullptr;   // skeleton word offsets e*3*S + s of component 0
+    const int* sk_ptr = nullptr;   // [n_sk + 1] CSR offsets: node i owns skeleton entries [ptr[i], ptr[i+1])
+    const int* kpos = nullptr;     // [NE][S] skeleton entry of (element, slot); entry k holds words 3k..3k+2
     const int* sk_node = nullptr;  // [n_sk] global node | kClampBit of every non-interior node
     int n_sk = 0;
     const Tables* tab;
@@ -158,7 +158,7 @@ struct pa_op {
     // unstructured mesh (pa_elast_setup_unstructured); kmap == nullptr on the box
     int* kmap = nullptr;             // device [NE][D^3] global node | kClampBit
     int* sk_ptr = nullptr;           // device CSR over the non-interior nodes
-    int* sk_idx = nullptr;
+    int* kpos = nullptr;
     int* sk_node = nullptr;
     int n_sk = 0;
     pa_solve_opts_t cached_opts;

@@ -120,14 +120,16 @@ extern "C" int pa_elast_setup_unstructured(int64_t num_vertices, const double* v
             sk_ptr.push_back(sk_ptr.back() + refs[n]);
         }
     const int n_sk = (int)sk_node.size();
-    std::vector<int> sk_idx((size_t)sk_ptr.back()), fillp(sk_ptr.begin(), sk_ptr.end() - 1);
+    // entry of every (element, slot): a node's entries follow its position in the list,
+    // in ascending element order
+    std::vector<int> kpos((size_t)NE * S), fillp(sk_ptr.begin(), sk_ptr.end() - 1);
     std::vector<int> kmap((size_t)NE * D3);
     for (int64_t e = 0; e < NE; ++e) {
         const int32_t* en = elem_nodes + (size_t)e * D3;
         for (int a = 0; a < D3; ++a) {
             const int n = en[a];
             kmap[(size_t)e * D3 + a] = (int)(n | ((clamped && clamped[n]) ? kClampBit : 0u));
-            if (slot[a] >= 0) sk_idx[fillp[pos[n]]++] = (int)(e * 3 * S + slot[a]);   // ascending e per node
+            if (slot[a] >= 0) kpos[(size_t)e * S + slot[a]] = fillp[pos[n]]++;
         }
     }
     // map coefficients from the element corners
@@ -162,7 +164,7 @@ extern "C" int pa_elast_setup_unstructured(int64_t num_vertices, const double* v
     if (!rc) rc = finish_geometry(op, coef, lambda, mu);
     if (!rc) rc = upload(kmap, &op->kmap);
     if (!rc) rc = upload(sk_ptr, &op->sk_ptr);
-    if (!rc) rc = upload(sk_idx, &op->sk_idx);
+    if (!rc) rc = upload(kpos, &op->kpos);
     if (!rc) rc = upload(sk_node, &op->sk_node);
     if (rc) {
         pa_elast_destroy(op);
