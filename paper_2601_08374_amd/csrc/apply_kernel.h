@@ -29,6 +29,14 @@
 // transposes between sweeps, with odd row strides against bank conflicts; the
 // x lines of component c+1 are loaded while component c is being contracted.
 // Several elements share a workgroup at low p to fill 64-wide wavefronts.
+//
+// Compile-time variants of the same kernel (the pointwise stage and the node
+// addressing change, the sweeps do not): MAT selects the material data (per-element
+// Lame parameters, per-point Lame parameters, per-element anisotropic Voigt
+// stiffness); GEO the element geometry (affine J^{-1} per element, J^{-1} and w det J
+// stored per quadrature point, or the trilinear map recomputed per point); UNS an
+// unstructured mesh, whose nodes come from an explicit element-to-node map and whose
+// element-boundary contributions are summed by pa_uns_gather_kernel.
 #pragma once
 
 #include <hip/hip_runtime.h>
