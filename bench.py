@@ -108,6 +108,43 @@ def cpu_baseline(ps, budget_s: float = 25.0):
             "per_p": res}
 
 
+def measured_ceilings(torch, dev, reps: int = 5):
+    """Attainable rates measured on the device: vector FMA throughput in FP64 and FP32
+    (pa_probe_fma, 8 independent chains per lane) and a plain 1 GiB device-to-device copy
+    (torch; 2 GiB moved per copy).  HIP events on the current stream."""
+    import ctypes as C
+    from paper_2601_08374_amd import capi
+    stream = torch.cuda.current_stream()
+    out = {}
+
+    def timed(fn):
+        fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    blocks, iters = 256 * 32, 2048
+    for dname, dtype, tdt in (("f64", 0, torch.float64), ("f32", 1, torch.float32)):
+        buf = torch.empty(blocks * 256, dtype=tdt, device=dev)
+        t = timed(lambda: capi.check(capi.pa_probe_fma(C.c_void_p(buf.data_ptr()), dtype, blocks, iters,
+                                                       C.c_void_p(stream.cuda_stream))))
+        out[f"fma_{dname}_tflops"] = round(4096 * blocks * iters / t / 1e12, 2)
+        del buf
+    n = 1 << 27
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    t = timed(lambda: b.copy_(a))
+    out["copy_gbs"] = round(2 * 8 * n / t / 1e9, 1)
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +163,10 @@ def main(argv=None):
     ap.add_argument("--profile-apply", type=int, default=0, metavar="P",
                     help="profiling mode: only run --reps applies of the degree-P sheared-box operator "
                          "(then three 256 MiB copies that calibrate the traffic counters) and exit")
+    ap.add_argument("--profile-solve", type=int, default=0, metavar="P",
+                    help="profiling mode: build the degree-P cantilever hierarchy, run one GMG-PCG solve "
+                         "(--solve-mode) to rtol 1e-8 and exit")
+    ap.add_argument("--solve-mode", choices=("f64", "f32_ir", "f32_prec"), default="f64")
     ap.add_argument("--dtype", choices=("f64", "f32"), default="f64")
     ap.add_argument("--reps", type=int, default=10)
     args = ap.parse_args(argv)
@@ -172,6 +213,25 @@ def main(argv=None):
         torch.cuda.synchronize()
         print(json.dumps({"profile_apply": args.profile_apply, "dtype": args.dtype, "reps": args.reps,
                           "N": s["N"], "NE": s["NE"], "calibration_copy_bytes": a.numel() * 8}), flush=True)
+        return 0
+
+    if args.profile_solve:
+        p = args.profile_solve
+        mesh = syn.cantilever_mesh(80, 8, 8)
+        lam, mu = (float(v) for v in syn.lame_from_young_poisson(1.0, 0.3))
+        op = pa.Operator(mesh, p, np.full(mesh.num_elements, lam), np.full(mesh.num_elements, mu))
+        b = op.rhs((0.0, 0.0, 0.0), 1, (0.0, 0.0, -1.0))
+        mode = {"f64": pa.PA_SOLVE_F64, "f32_ir": pa.PA_SOLVE_F32_IR, "f32_prec": pa.PA_SOLVE_F32_PREC}[args.solve_mode]
+        H = op.hierarchy(mode=mode, stop=pa.PA_STOP_TRUE, cheb_degree=3, h_levels=2)
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info, rc = H.pcg(b, x, rtol=1e-8)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        print(json.dumps({"profile_solve": p, "mode": args.solve_mode, "rc": rc, "iters": info.iters,
+                          "outer": info.outer_iters, "rel_res_true": info.rel_res_true, "solve_s": t,
+                          "N": op.N}), flush=True)
         return 0
 
     # ---------------- timed step: FP64 apply at every p of the sweep
@@ -223,6 +283,11 @@ def main(argv=None):
                 "hbm_gbs": round(algorithmic_bytes(sd["N"], sd["NE"], 8) / t_launch / 1e9, 1),
                 "launch_us": round(t_launch * 1e6, 2), "source_hash": src_hash}
 
+    log("measured ceilings (FMA probe, copy)")
+    ceilings = measured_ceilings(torch, dev)
+    roofline["measured_peak"] = ceilings["fma_f64_tflops"]
+    roofline["frac_measured"] = round(achieved / ceilings["fma_f64_tflops"], 4)
+
     result = {
         "metric": "PA apply GDoF/s at p=1..8 (FP64 vs FP32); GMG-PCG solves/s + p99 latency",
         "value": round(value, 4), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -234,6 +299,7 @@ def main(argv=None):
                    "dofs": {p: setups[p]["N"] for p in STEP_PS}, "parallelism": "single GPU"},
         "step_per_p_gdofs": {p: round(setups[p]["N"] / (per_p_ms[p] * 1e-3) / 1e9, 3) for p in STEP_PS},
         "roofline": roofline,
+        "ceilings": ceilings,
     }
     for p in STEP_PS:
         for k in ("xs", "ys"):
@@ -273,6 +339,7 @@ def main(argv=None):
                 sweep[p][name] = {"gdofs": round(s["N"] / t / 1e9, 3), "gdofs_hot": round(s["N"] / th / 1e9, 3),
                                   "us": round(t * 1e6, 2), "tflops": round(fl / t / 1e12, 3),
                                   "frac_alu_peak": round(fl / t / 1e12 / peak, 4),
+                                  "frac_alu_measured": round(fl / t / 1e12 / ceilings[f"fma_{name}_tflops"], 4),
                                   "gbs": round(by / t / 1e9, 1), "frac_hbm": round(by / t / 1e9 / PEAK_HBM_GBS, 4),
                                   "N": s["N"]}
                 del s

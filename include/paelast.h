@@ -295,6 +295,16 @@ int gmg_pcg_step(pa_solve_t* s, int n_iters);
 int gmg_pcg_poll(pa_solve_t* s, int* done, int* status);
 int gmg_pcg_end(pa_solve_t* s, pa_solve_info_t* info);
 
+/* ---- measurement ------------------------------------------------------------ */
+/* Attainable vector FMA rate (a measured ceiling beside the published peak, for the
+ * roofline of the apply kernels; not part of the method).  Launches blocks x 256
+ * lanes on hip_stream, each running 8 independent chains of iters dependent FMAs in
+ * dtype (PA_F64 / PA_F32, non-packed), i.e. 4096 * blocks * iters FLOPs, and writes
+ * one value per lane to out, a device array of blocks * 256 words of dtype owned by
+ * the caller.  Asynchronous; time it with events on the same stream.  PA_EINVAL for
+ * out == NULL, another dtype, blocks < 1 or iters < 1. */
+int pa_probe_fma(void* out, int dtype, int blocks, int iters, void* hip_stream);
+
 /* ---- errors ----------------------------------------------------------------- */
 const char* pa_last_error(void);
 

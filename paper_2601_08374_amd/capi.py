@@ -104,6 +104,7 @@ SIGNATURES = {
     "gmg_pcg_step": (_i, [_vp, _i]),
     "gmg_pcg_poll": (_i, [_vp, C.POINTER(_i), C.POINTER(_i)]),
     "gmg_pcg_end": (_i, [_vp, C.POINTER(pa_solve_info_t)]),
+    "pa_probe_fma": (_i, [_vp, _i, _i, _i, _vp]),
     "pa_last_error": (C.c_char_p, []),
 }
 

@@ -212,30 +212,28 @@ int smooth(pa_gmg* G, int l, const void* b, void* x, bool zero) {
     const double sigma = theta / delta;
     double rho = 1.0 / sigma;
     int rc;
-    if (zero) {
-        if ((rc = launch_fill(x, v.dtype, v.N, 0.0, s))) return rc;
-        if ((rc = launch_copy(v.r, b, v.dtype, v.N, s))) return rc;
-    } else {
-        if ((rc = level_apply(v, x, v.t))) return rc;
-        if ((rc = launch_residual(v.r, b, v.t, v.dtype, v.N, s))) return rc;
-    }
-    if ((rc = launch_cheb_first(v.d, v.dinv, v.r, 1.0 / theta, v.dtype, v.N, s))) return rc;
-    for (int j = 0; j < k; ++j) {
-        if (j == k - 1) return launch_add(x, v.d, v.dtype, v.N, s);
+    // r = b - A x (r = b from x = 0) and the first direction d = dinv r / theta, in one pass
+    if (!zero && (rc = level_apply(v, x, v.t))) return rc;
+    if ((rc = launch_cheb_start(v.r, v.d, v.dinv, b, zero ? nullptr : v.t, 1.0 / theta, v.dtype, v.N, s))) return rc;
+    if (k == 1) return zero ? launch_copy(x, v.d, v.dtype, v.N, s) : launch_add(x, v.d, v.dtype, v.N, s);
+    for (int j = 0; j + 1 < k; ++j) {
         if ((rc = level_apply(v, v.d, v.t))) return rc;
         const double rho_n = 1.0 / (2.0 * sigma - rho);
-        if ((rc = launch_cheb_step(x, v.r, v.t, v.d, v.dinv, rho_n * rho, 2.0 * rho_n / delta, v.dtype, v.N, s)))
+        // the first step sets x = d when x started at 0; the last one also adds the final d
+        if ((rc = launch_cheb_step(x, v.r, v.t, v.d, v.dinv, rho_n * rho, 2.0 * rho_n / delta, zero && j == 0,
+                                   j + 2 == k, v.dtype, v.N, s)))
             return rc;
         rho = rho_n;
     }
     return PA_OK;
 }
 
-int restrict_to(pa_gmg* G, int l, const void* rf, void* rc) {
+// rc = R (rf - tf), tf optional: the residual b - A x restricted without storing it.
+int restrict_to(pa_gmg* G, int l, const void* rf, void* rc, const void* tf = nullptr) {
     Level& f = G->L[l];
     Level& c = G->L[l + 1];
-    if (f.tkind == 0) return launch_p_restrict(rf, rc, f.Ip, c.op->p, f.op->p, c.g, f.g, f.dtype, G->stream);
-    return launch_h_restrict(rf, rc, f.hax, c.g, f.g, f.dtype, G->stream);
+    if (f.tkind == 0) return launch_p_restrict(rf, tf, rc, f.Ip, c.op->p, f.op->p, c.g, f.g, f.dtype, G->stream);
+    return launch_h_restrict(rf, tf, rc, f.hax, c.g, f.g, f.dtype, G->stream);
 }
 
 int prolong_to(pa_gmg* G, int l, const void* xc, void* xf, int add) {
@@ -257,8 +255,7 @@ int vcycle(pa_gmg* G, int l, const void* b, void* x) {
     int rc;
     if ((rc = smooth(G, l, b, x, true))) return rc;
     if ((rc = level_apply(v, x, v.t))) return rc;
-    if ((rc = launch_residual(v.r, b, v.t, v.dtype, v.N, G->stream))) return rc;
-    if ((rc = restrict_to(G, l, v.r, c.b))) return rc;
+    if ((rc = restrict_to(G, l, b, c.b, v.t))) return rc;   // c.b = R (b - A x)
     if ((rc = vcycle(G, l + 1, c.b, c.x))) return rc;
     if ((rc = prolong_to(G, l, c.x, x, 1))) return rc;
     return smooth(G, l, b, x, false);

@@ -44,8 +44,10 @@ int launch_copy(void* y, const void* x, int dtype, int64_t n, hipStream_t s);
 int launch_cast_scale(void* y, int dty, const void* x, int dtx, const double* sc, int slot, int inv_sqrt, int64_t n,
                       hipStream_t s);
 int launch_ir_update(double* x, const void* d, int dtd, const double* sc, int slot, int64_t n, hipStream_t s);
-int launch_cheb_step(void* x, void* r, const void* t, void* d, const void* dinv, double c1, double c2, int dtype,
-                     int64_t n, hipStream_t s);
+int launch_cheb_step(void* x, void* r, const void* t, void* d, const void* dinv, double c1, double c2, bool x_zero,
+                     bool last, int dtype, int64_t n, hipStream_t s);
+int launch_cheb_start(void* r, void* d, const void* dinv, const void* b, const void* t, double c, int dtype,
+                      int64_t n, hipStream_t s);
 int launch_cheb_first(void* d, const void* dinv, const void* r, double c, int dtype, int64_t n, hipStream_t s);
 int launch_add(void* y, const void* x, int dtype, int64_t n, hipStream_t s);
 int launch_reciprocal(void* y, int dtype, int64_t n, hipStream_t s);
@@ -53,11 +55,11 @@ int launch_splitmix(void* v, int dtype, uint64_t seed, int64_t n, hipStream_t s)
 int launch_p_interp_matrix(const double* gll_c, const double* gll_f, int pc, int pf, double* I, hipStream_t s);
 int launch_p_prolong(const void* xc, void* xf, const double* I, int pc, int pf, const Geom& gc, const Geom& gf,
                      int add, int dtype, hipStream_t s);
-int launch_p_restrict(const void* rf, void* rc, const double* I, int pc, int pf, const Geom& gc, const Geom& gf,
+int launch_p_restrict(const void* rf, const void* tf, void* rc, const double* I, int pc, int pf, const Geom& gc, const Geom& gf,
                       int dtype, hipStream_t s);
 int launch_h_prolong(const void* xc, void* xf, const HAxis ax[3], const Geom& gc, const Geom& gf, int add, int dtype,
                      hipStream_t s);
-int launch_h_restrict(const void* rf, void* rc, const HAxis ax[3], const Geom& gc, const Geom& gf, int dtype,
+int launch_h_restrict(const void* rf, const void* tf, void* rc, const HAxis ax[3], const Geom& gc, const Geom& gf, int dtype,
                       hipStream_t s);
 int launch_coarse_assemble(double* A, int N, const pa_op* op, hipStream_t s);
 int coarse_invert(double* A, double* col, int N, hipStream_t s);

@@ -189,17 +189,37 @@ __global__ void ir_update_kernel(double* __restrict__ x, const TI* __restrict__ 
     GRID_STRIDE(i, n) x[i] += f * (double)d[i];
 }
 
-// Chebyshev step: x += d; r -= t; d = c1*d + c2*dinv*r
-template <typename T>
+// Chebyshev step: x += d (x = d when XZERO: the smoother started from x = 0);
+// r -= t; d = c1*d + c2*dinv*r.  LAST: the smoother's final update x += d is folded
+// in (x = (x + d) + d_new) and r, d are not written back (dead afterwards).
+template <typename T, bool XZERO, bool LAST>
 __global__ void cheb_step_kernel(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ t, T* __restrict__ d,
                                  const T* __restrict__ dinv, double c1, double c2, int64_t n) {
     const T a = (T)c1, b = (T)c2;
     GRID_STRIDE(i, n) {
         const T dv = d[i];
-        x[i] += dv;
+        const T xv = XZERO ? dv : x[i] + dv;
         const T rv = r[i] - t[i];
+        const T dn = a * dv + b * dinv[i] * rv;
+        if (LAST) {
+            x[i] = xv + dn;
+        } else {
+            x[i] = xv;
+            r[i] = rv;
+            d[i] = dn;
+        }
+    }
+}
+
+// Start of the smoother: r = b - t (or r = b when t is null: x = 0); d = c*dinv*r.
+template <typename T>
+__global__ void cheb_start_kernel(T* __restrict__ r, T* __restrict__ d, const T* __restrict__ dinv,
+                                  const T* __restrict__ b, const T* __restrict__ t, double c, int64_t n) {
+    const T tc = (T)c;
+    GRID_STRIDE(i, n) {
+        const T rv = t ? b[i] - t[i] : b[i];
         r[i] = rv;
-        d[i] = a * dv + b * dinv[i] * rv;
+        d[i] = tc * dinv[i] * rv;
     }
 }
 
@@ -316,8 +336,8 @@ __global__ void p_prolong_kernel(const T* __restrict__ xc, T* __restrict__ xf, c
 }
 
 template <typename T>
-__global__ void p_restrict_kernel(const T* __restrict__ rf, T* __restrict__ rc, const double* __restrict__ I, int pc,
-                                  int pf, Geom gc, Geom gf) {
+__global__ void p_restrict_kernel(const T* __restrict__ rf, const T* __restrict__ tf, T* __restrict__ rc,
+                                  const double* __restrict__ I, int pc, int pf, Geom gc, Geom gf) {
     extern __shared__ double sm[];
     const int Dc = pc + 1, Df = pf + 1;
     const int Df3 = Df * Df * Df;
@@ -333,8 +353,8 @@ __global__ void p_restrict_kernel(const T* __restrict__ rf, T* __restrict__ rc, 
         const int ix = a % Df, iy = (a / Df) % Df, iz = a / (Df * Df);
         double v = 0.0;
         if (owns(ex, ix, gf.nx, pf) && owns(ey, iy, gf.ny, pf) && owns(ez, iz, gf.nz, pf)) {
-            const int node = (ex * pf + ix) + gf.Nx * ((ey * pf + iy) + gf.Ny * (ez * pf + iz));
-            v = (double)rf[(size_t)c * gf.Nn + node];
+            const size_t o = (size_t)c * gf.Nn + (ex * pf + ix) + gf.Nx * ((ey * pf + iy) + gf.Ny * (ez * pf + iz));
+            v = tf ? (double)(rf[o] - tf[o]) : (double)rf[o];
         }
         X[w] = v;
     }
@@ -411,8 +431,8 @@ __global__ void h_prolong_kernel(const T* __restrict__ xc, T* __restrict__ xf, H
 }
 
 template <typename T>
-__global__ void h_restrict_kernel(const T* __restrict__ rf, T* __restrict__ rc, HAxis ax, HAxis ay, HAxis az, Geom gc,
-                                  Geom gf) {
+__global__ void h_restrict_kernel(const T* __restrict__ rf, const T* __restrict__ tf, T* __restrict__ rc, HAxis ax,
+                                  HAxis ay, HAxis az, Geom gc, Geom gf) {
     GRID_STRIDE(node, (int64_t)gc.Nn) {
         const int jx = (int)(node % gc.Nx), jy = (int)((node / gc.Nx) % gc.Ny), jz = (int)(node / ((int64_t)gc.Nx * gc.Ny));
         const bool cl = clamped_node(gc.clamp, jx, jy, jz, gc);
@@ -428,9 +448,9 @@ __global__ void h_restrict_kernel(const T* __restrict__ rf, T* __restrict__ rc, 
                         for (int d = 0; d < 3; ++d) {
                             const double wx = ax.fw[jx * 3 + d];
                             if (wx == 0.0) continue;
-                            acc += wx * wy * wz *
-                                   (double)rf[(size_t)c * gf.Nn + ax.fi[jx * 3 + d] +
-                                              gf.Nx * (ay.fi[jy * 3 + b] + gf.Ny * az.fi[jz * 3 + a])];
+                            const size_t o = (size_t)c * gf.Nn + ax.fi[jx * 3 + d] +
+                                             gf.Nx * (ay.fi[jy * 3 + b] + gf.Ny * az.fi[jz * 3 + a]);
+                            acc += wx * wy * wz * (tf ? (double)(rf[o] - tf[o]) : (double)rf[o]);
                         }
                     }
                 }
@@ -668,14 +688,42 @@ int launch_ir_update(double* x, const void* d, int dtd, const double* sc, int sl
     return PA_OK;
 }
 
-int launch_cheb_step(void* x, void* r, const void* t, void* d, const void* dinv, double c1, double c2, int dtype,
-                     int64_t n, hipStream_t s) {
-    if (dtype == PA_F64)
-        hipLaunchKernelGGL(cheb_step_kernel<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<double>(x),
-                           mp<double>(r), cp<double>(t), mp<double>(d), cp<double>(dinv), c1, c2, n);
+template <typename T>
+void cheb_step_dispatch(void* x, void* r, const void* t, void* d, const void* dinv, double c1, double c2, bool x_zero,
+                        bool last, int64_t n, hipStream_t s) {
+    const dim3 g(grid_for(n)), b(kBlock);
+    if (x_zero && last)
+        hipLaunchKernelGGL((cheb_step_kernel<T, true, true>), g, b, 0, s, mp<T>(x), mp<T>(r), cp<T>(t), mp<T>(d),
+                           cp<T>(dinv), c1, c2, n);
+    else if (x_zero)
+        hipLaunchKernelGGL((cheb_step_kernel<T, true, false>), g, b, 0, s, mp<T>(x), mp<T>(r), cp<T>(t), mp<T>(d),
+                           cp<T>(dinv), c1, c2, n);
+    else if (last)
+        hipLaunchKernelGGL((cheb_step_kernel<T, false, true>), g, b, 0, s, mp<T>(x), mp<T>(r), cp<T>(t), mp<T>(d),
+                           cp<T>(dinv), c1, c2, n);
     else
-        hipLaunchKernelGGL(cheb_step_kernel<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<float>(x), mp<float>(r),
-                           cp<float>(t), mp<float>(d), cp<float>(dinv), c1, c2, n);
+        hipLaunchKernelGGL((cheb_step_kernel<T, false, false>), g, b, 0, s, mp<T>(x), mp<T>(r), cp<T>(t), mp<T>(d),
+                           cp<T>(dinv), c1, c2, n);
+}
+
+int launch_cheb_step(void* x, void* r, const void* t, void* d, const void* dinv, double c1, double c2, bool x_zero,
+                     bool last, int dtype, int64_t n, hipStream_t s) {
+    if (dtype == PA_F64)
+        cheb_step_dispatch<double>(x, r, t, d, dinv, c1, c2, x_zero, last, n, s);
+    else
+        cheb_step_dispatch<float>(x, r, t, d, dinv, c1, c2, x_zero, last, n, s);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_cheb_start(void* r, void* d, const void* dinv, const void* b, const void* t, double c, int dtype,
+                      int64_t n, hipStream_t s) {
+    if (dtype == PA_F64)
+        hipLaunchKernelGGL(cheb_start_kernel<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<double>(r),
+                           mp<double>(d), cp<double>(dinv), cp<double>(b), cp<double>(t), c, n);
+    else
+        hipLaunchKernelGGL(cheb_start_kernel<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<float>(r),
+                           mp<float>(d), cp<float>(dinv), cp<float>(b), cp<float>(t), c, n);
     PA_CHECK_LAUNCH();
     return PA_OK;
 }
@@ -744,16 +792,16 @@ int launch_p_prolong(const void* xc, void* xf, const double* I, int pc, int pf, 
     return PA_OK;
 }
 
-int launch_p_restrict(const void* rf, void* rc, const double* I, int pc, int pf, const Geom& gc, const Geom& gf,
+int launch_p_restrict(const void* rf, const void* tf, void* rc, const double* I, int pc, int pf, const Geom& gc, const Geom& gf,
                       int dtype, hipStream_t s) {
     int rcode = launch_fill(rc, dtype, 3 * (int64_t)gc.Nn, 0.0, s);
     if (rcode) return rcode;
     const size_t lds = p_transfer_lds(pc, pf);
     if (dtype == PA_F64)
-        hipLaunchKernelGGL(p_restrict_kernel<double>, dim3(gf.NE), dim3(128), lds, s, cp<double>(rf), mp<double>(rc),
+        hipLaunchKernelGGL(p_restrict_kernel<double>, dim3(gf.NE), dim3(128), lds, s, cp<double>(rf), cp<double>(tf), mp<double>(rc),
                            I, pc, pf, gc, gf);
     else
-        hipLaunchKernelGGL(p_restrict_kernel<float>, dim3(gf.NE), dim3(128), lds, s, cp<float>(rf), mp<float>(rc), I,
+        hipLaunchKernelGGL(p_restrict_kernel<float>, dim3(gf.NE), dim3(128), lds, s, cp<float>(rf), cp<float>(tf), mp<float>(rc), I,
                            pc, pf, gc, gf);
     PA_CHECK_LAUNCH();
     return PA_OK;
@@ -772,14 +820,14 @@ int launch_h_prolong(const void* xc, void* xf, const HAxis ax[3], const Geom& gc
     return PA_OK;
 }
 
-int launch_h_restrict(const void* rf, void* rc, const HAxis ax[3], const Geom& gc, const Geom& gf, int dtype,
+int launch_h_restrict(const void* rf, const void* tf, void* rc, const HAxis ax[3], const Geom& gc, const Geom& gf, int dtype,
                       hipStream_t s) {
     const int g = grid_for(gc.Nn);
     if (dtype == PA_F64)
-        hipLaunchKernelGGL(h_restrict_kernel<double>, dim3(g), dim3(kBlock), 0, s, cp<double>(rf), mp<double>(rc),
+        hipLaunchKernelGGL(h_restrict_kernel<double>, dim3(g), dim3(kBlock), 0, s, cp<double>(rf), cp<double>(tf), mp<double>(rc),
                            ax[0], ax[1], ax[2], gc, gf);
     else
-        hipLaunchKernelGGL(h_restrict_kernel<float>, dim3(g), dim3(kBlock), 0, s, cp<float>(rf), mp<float>(rc), ax[0],
+        hipLaunchKernelGGL(h_restrict_kernel<float>, dim3(g), dim3(kBlock), 0, s, cp<float>(rf), cp<float>(tf), mp<float>(rc), ax[0],
                            ax[1], ax[2], gc, gf);
     PA_CHECK_LAUNCH();
     return PA_OK;
