@@ -670,25 +670,8 @@ pa_skeleton_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __restri
     if (node >= g.Nn) return;
     const int gx = node % g.Nx, r = node / g.Nx;
     const int gy = r % g.Ny, gz = r / g.Ny;
-    const int rx = gx % P, ry = gy % P, rz = gz % P;
-    if (rx != 0 && ry != 0 && rz != 0) return;   // interior node: written by its element
-    // Per axis two candidate (element, local index) pairs: the element before the node
-    // (local index P) and the element containing it from the left (local index 0); a
-    // node strictly inside an element along the axis has one (valid) candidate.
-    int e_[3][2], l_[3][2];
-    bool v_[3][2];
-    const int gg[3] = {gx, gy, gz}, rr[3] = {rx, ry, rz}, nn[3] = {g.nx, g.ny, g.nz};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int q = gg[a] / P;
-        if (rr[a] != 0) {
-            e_[a][0] = q; l_[a][0] = rr[a]; v_[a][0] = true;
-            e_[a][1] = q; l_[a][1] = rr[a]; v_[a][1] = false;
-        } else {
-            e_[a][0] = q - 1; l_[a][0] = P; v_[a][0] = q > 0;
-            e_[a][1] = q; l_[a][1] = 0; v_[a][1] = q < nn[a];
-        }
-    }
+    if (gx % P != 0 && gy % P != 0 && gz % P != 0) return;   // interior node: written by its element
+    const NodeCands nc = node_candidates(g, P, gx, gy, gz);
     const size_t NN = (size_t)g.Nn;
     const bool cl = g.clamp && clamped_node(g.clamp, gx, gy, gz, g);
     T acc[3] = {T(0), T(0), T(0)};
@@ -700,9 +683,9 @@ pa_skeleton_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __restri
             for (int ky = 0; ky < 2; ++ky)
 #pragma unroll
                 for (int kx = 0; kx < 2; ++kx) {
-                    if (!(v_[0][kx] && v_[1][ky] && v_[2][kz])) continue;
-                    const int e = e_[0][kx] + g.nx * (e_[1][ky] + g.ny * e_[2][kz]);
-                    const int s = SK::index(l_[0][kx], l_[1][ky], l_[2][kz]);
+                    if (!(nc.v[0][kx] && nc.v[1][ky] && nc.v[2][kz])) continue;
+                    const int e = nc.e[0][kx] + g.nx * (nc.e[1][ky] + g.ny * nc.e[2][kz]);
+                    const int s = SK::index(nc.l[0][kx], nc.l[1][ky], nc.l[2][kz]);
 #pragma unroll
                     for (int c = 0; c < 3; ++c) acc[c] += sk[SK::offset(e, c, s, g.NE)];
                 }

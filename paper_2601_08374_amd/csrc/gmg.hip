@@ -133,6 +133,7 @@ struct Level {
     double lam_hat = 0.0, lmax = 0.0, lmin = 0.0;
     int tkind = -1;
     double* Ip = nullptr;
+    void* skr = nullptr;   // p-restriction: element-boundary coarse entries [NE][3][slots of the coarse element]
     HAxis hax[3];
     void* hbuf = nullptr;
 };
@@ -182,7 +183,7 @@ namespace pa {
 namespace {
 
 void free_level(Level& v) {
-    for (void* p : {v.dinv, v.b, v.x, v.r, v.d, v.t, (void*)v.Ip, v.hbuf})
+    for (void* p : {v.dinv, v.b, v.x, v.r, v.d, v.t, (void*)v.Ip, v.skr, v.hbuf})
         if (p) (void)hipFree(p);
     if (v.op) pa_elast_destroy(v.op);
     v = Level();
@@ -232,7 +233,7 @@ int smooth(pa_gmg* G, int l, const void* b, void* x, bool zero) {
 int restrict_to(pa_gmg* G, int l, const void* rf, void* rc, const void* tf = nullptr) {
     Level& f = G->L[l];
     Level& c = G->L[l + 1];
-    if (f.tkind == 0) return launch_p_restrict(rf, tf, rc, f.Ip, c.op->p, f.op->p, c.g, f.g, f.dtype, G->stream);
+    if (f.tkind == 0) return launch_p_restrict(rf, tf, rc, f.skr, f.Ip, c.op->p, f.op->p, c.g, f.g, f.dtype, G->stream);
     return launch_h_restrict(rf, tf, rc, f.hax, c.g, f.g, f.dtype, G->stream);
 }
 
@@ -313,6 +314,13 @@ int build_transfer(pa_gmg* G, int l, const LevelPlan& pf, const LevelPlan& pc) {
     if (pf.kind == 0) {
         const int Df = f.op->p + 1, Dc = c.op->p + 1;
         if (hipMalloc(&f.Ip, Df * Dc * sizeof(double)) != hipSuccess) return fail(PA_ENOMEM, "transfer alloc");
+        const size_t slots = (size_t)Dc * Dc * Dc - (size_t)(Dc - 2) * (Dc - 2) * (Dc - 2);
+        const size_t esz = f.dtype == PA_F64 ? sizeof(double) : sizeof(float);
+        if (hipMalloc(&f.skr, (size_t)f.g.NE * 3 * slots * esz) != hipSuccess) {
+            (void)hipGetLastError();
+            f.skr = nullptr;
+            return fail(PA_ENOMEM, "transfer alloc");
+        }
         return launch_p_interp_matrix(c.op->d_tab, f.op->d_tab, c.op->p, f.op->p, f.Ip, s);
     }
     // h-transfer tables

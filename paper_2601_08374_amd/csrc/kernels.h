@@ -14,6 +14,34 @@ __device__ __forceinline__ bool clamped_node(uint32_t m, int gx, int gy, int gz,
            ((m & 8u) && gy == g.Ny - 1) || ((m & 16u) && gz == 0) || ((m & 32u) && gz == g.Nz - 1);
 }
 
+// The elements of the degree-p box that contain node (gx, gy, gz), and the node's local
+// index in each: per axis two candidates, the element before (local index p) and the
+// element after (local index 0) when the node lies on an element boundary along that
+// axis, a single valid one when it lies strictly inside an element.  Summing over the
+// valid (x, y, z) combinations in a fixed order gives deterministic node sums.
+struct NodeCands {
+    int e[3][2], l[3][2];
+    bool v[3][2];
+};
+__device__ __forceinline__ NodeCands node_candidates(const Geom& g, int p, int gx, int gy, int gz) {
+    NodeCands c;
+    const int gg[3] = {gx, gy, gz}, nn[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int q = gg[a] / p, r = gg[a] % p;
+        if (r != 0) {
+            c.e[a][0] = c.e[a][1] = q;
+            c.l[a][0] = c.l[a][1] = r;
+            c.v[a][0] = true;
+            c.v[a][1] = false;
+        } else {
+            c.e[a][0] = q - 1; c.l[a][0] = p; c.v[a][0] = q > 0;
+            c.e[a][1] = q; c.l[a][1] = 0; c.v[a][1] = q < nn[a];
+        }
+    }
+    return c;
+}
+
 // setup.hip
 int tables_words(int p, int q);
 int compute_tables(int p, int q, hipStream_t s, double** d_tab, Tables* host);

@@ -197,14 +197,10 @@ int compute_element_data(const MeshDesc& m, const double* d_vert, const double* 
 //   P = J^{-T} M J^{-1} (P_cd = int d_c phi_a d_d phi_a / det J);
 //   diag(c,a) += detJ*lambda P_cc + detJ*mu (tr P + P_cc).
 // ---------------------------------------------------------------------------
+// Contribution of element e to the diagonal at its local node (ix, iy, iz), component c.
 template <typename T>
-__global__ void diagonal_kernel(T* __restrict__ dg, const T* __restrict__ ed, const double* __restrict__ tab,
-                                int p, int q, Geom g) {
-    const int D = p + 1, D3 = D * D * D;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long long)g.NE * D3) return;
-    const int e = (int)(t / D3), a = (int)(t % D3);
-    const int ix = a % D, iy = (a / D) % D, iz = a / (D * D);
+__device__ __forceinline__ void diagonal_part(const T* __restrict__ ed, const double* __restrict__ tab, int D, int q,
+                                              int e, int ix, int iy, int iz, double (&out)[3]) {
     const double* bb = tab + D + 2 * q + 2 * D * q;
     const double* bg = bb + D;
     const double* gg = bg + D;
@@ -232,18 +228,33 @@ __global__ void diagonal_kernel(T* __restrict__ dg, const T* __restrict__ ed, co
         tr += s;
     }
     const double lw = (double)o[9], mw = (double)o[10];
-    const int ex = e % g.nx, ey = (e / g.nx) % g.ny, ez = e / (g.nx * g.ny);
-    const int node = (ex * p + ix) + g.Nx * ((ey * p + iy) + g.Ny * (ez * p + iz));
-    for (int c = 0; c < 3; ++c) unsafeAtomicAdd(dg + (size_t)c * g.Nn + node, (T)(lw * P[c] + mw * (tr + P[c])));
+    for (int c = 0; c < 3; ++c) out[c] = lw * P[c] + mw * (tr + P[c]);
+}
+
+// One thread per node: the contributions of its elements summed in a fixed order.
+template <typename T>
+__global__ void diagonal_kernel(T* __restrict__ dg, const T* __restrict__ ed, const double* __restrict__ tab,
+                                int p, int q, Geom g) {
+    const int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= g.Nn) return;
+    const int gx = node % g.Nx, gy = (node / g.Nx) % g.Ny, gz = node / (g.Nx * g.Ny);
+    const NodeCands nc = node_candidates(g, p, gx, gy, gz);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int kz = 0; kz < 2; ++kz)
+        for (int ky = 0; ky < 2; ++ky)
+            for (int kx = 0; kx < 2; ++kx) {
+                if (!(nc.v[0][kx] && nc.v[1][ky] && nc.v[2][kz])) continue;
+                const int e = nc.e[0][kx] + g.nx * (nc.e[1][ky] + g.ny * nc.e[2][kz]);
+                double part[3];
+                diagonal_part(ed, tab, p + 1, q, e, nc.l[0][kx], nc.l[1][ky], nc.l[2][kz], part);
+                for (int c = 0; c < 3; ++c) acc[c] += part[c];
+            }
+    for (int c = 0; c < 3; ++c) dg[(size_t)c * g.Nn + node] = (T)acc[c];
 }
 
 int launch_diagonal(const pa_op* op, void* d, int constrained) {
     const Geom g = make_geom(op->mesh, op->p, constrained != 0);
-    const int D = op->p + 1;
-    int rc = launch_fill(d, op->dtype, op->N, 0.0, op->stream);
-    if (rc) return rc;
-    const long long work = (long long)g.NE * D * D * D;
-    const int nb = (int)((work + 255) / 256);
+    const int nb = (g.Nn + 255) / 256;
     if (op->dtype == PA_F64)
         hipLaunchKernelGGL(diagonal_kernel<double>, dim3(nb), dim3(256), 0, op->stream, (double*)d,
                            (const double*)op->ed, op->d_tab, op->p, op->q, g);
@@ -261,15 +272,11 @@ int launch_diagonal(const pa_op* op, void* d, int constrained) {
 // (similarly y, z): int phi_a dGamma = |J e_t1 x J e_t2| sB[i_t1] sB[i_t2] for
 // nodes on the face (l_i at the end point is 1 for the end node, 0 otherwise).
 // ---------------------------------------------------------------------------
-__global__ void rhs_kernel(double* __restrict__ b, const double* __restrict__ vert, const double* __restrict__ tab,
-                           Mat3 A, int p, int q, Geom g, double fx, double fy, double fz, int face, double tx,
-                           double ty, double tz) {
-    const int D = p + 1, D3 = D * D * D;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long long)g.NE * D3) return;
-    const int e = (int)(t / D3), a = (int)(t % D3);
-    const int idx[3] = {a % D, (a / D) % D, a / (D * D)};
-    const int ex = e % g.nx, ey = (e / g.nx) % g.ny, ez = e / (g.nx * g.ny);
+__device__ __forceinline__ void rhs_part(const double* __restrict__ vert, const double* __restrict__ tab,
+                                         const Mat3& A, int p, int q, const Geom& g, int ex, int ey, int ez,
+                                         const int (&idx)[3], const double (&f)[3], int face, const double (&t)[3],
+                                         double (&out)[3]) {
+    const int D = p + 1;
     const int epos[3] = {ex, ey, ez};
     const int nel[3] = {g.nx, g.ny, g.nz};
     const double* vx = vert;
@@ -277,14 +284,11 @@ __global__ void rhs_kernel(double* __restrict__ b, const double* __restrict__ ve
     const double* vz = vy + g.ny + 1;
     const double h[3] = {vx[ex + 1] - vx[ex], vy[ey + 1] - vy[ey], vz[ez + 1] - vz[ez]};
     const double* sB = tab + D + 2 * q + 2 * D * q + 3 * D;
-    const int gx = ex * p + idx[0], gy = ey * p + idx[1], gz = ez * p + idx[2];
-    if (clamped_node(g.clamp, gx, gy, gz, g)) return;
-    const int node = gx + g.Nx * (gy + g.Ny * gz);
     const double* a9 = A.a;
     const double detA = a9[0] * (a9[4] * a9[8] - a9[5] * a9[7]) - a9[1] * (a9[3] * a9[8] - a9[5] * a9[6]) +
                         a9[2] * (a9[3] * a9[7] - a9[4] * a9[6]);
     const double vol = detA * h[0] * h[1] * h[2] * sB[idx[0]] * sB[idx[1]] * sB[idx[2]];
-    double c0 = fx * vol, c1 = fy * vol, c2 = fz * vol;
+    for (int c = 0; c < 3; ++c) out[c] = f[c] * vol;
     if (face >= 0) {
         const int ax = face / 2, side = face % 2;
         const int t1 = ax == 0 ? 1 : 0, t2 = ax == 2 ? 1 : 2;
@@ -295,25 +299,41 @@ __global__ void rhs_kernel(double* __restrict__ b, const double* __restrict__ ve
             const double v0 = a9[0 * 3 + t2], v1 = a9[1 * 3 + t2], v2 = a9[2 * 3 + t2];
             const double cx = u1 * v2 - u2 * v1, cy = u2 * v0 - u0 * v2, cz = u0 * v1 - u1 * v0;
             const double area = sqrt(cx * cx + cy * cy + cz * cz) * h[t1] * h[t2] * sB[idx[t1]] * sB[idx[t2]];
-            c0 += tx * area;
-            c1 += ty * area;
-            c2 += tz * area;
+            for (int c = 0; c < 3; ++c) out[c] += t[c] * area;
         }
     }
-    unsafeAtomicAdd(b + node, c0);
-    unsafeAtomicAdd(b + (size_t)g.Nn + node, c1);
-    unsafeAtomicAdd(b + 2 * (size_t)g.Nn + node, c2);
+}
+
+// One thread per node: the contributions of its elements summed in a fixed order;
+// clamped nodes get 0.
+__global__ void rhs_kernel(double* __restrict__ b, const double* __restrict__ vert, const double* __restrict__ tab,
+                           Mat3 A, int p, int q, Geom g, double fx, double fy, double fz, int face, double tx,
+                           double ty, double tz) {
+    const int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= g.Nn) return;
+    const int gx = node % g.Nx, gy = (node / g.Nx) % g.Ny, gz = node / (g.Nx * g.Ny);
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (!clamped_node(g.clamp, gx, gy, gz, g)) {
+        const NodeCands nc = node_candidates(g, p, gx, gy, gz);
+        const double f[3] = {fx, fy, fz}, t[3] = {tx, ty, tz};
+        for (int kz = 0; kz < 2; ++kz)
+            for (int ky = 0; ky < 2; ++ky)
+                for (int kx = 0; kx < 2; ++kx) {
+                    if (!(nc.v[0][kx] && nc.v[1][ky] && nc.v[2][kz])) continue;
+                    const int idx[3] = {nc.l[0][kx], nc.l[1][ky], nc.l[2][kz]};
+                    double part[3];
+                    rhs_part(vert, tab, A, p, q, g, nc.e[0][kx], nc.e[1][ky], nc.e[2][kz], idx, f, face, t, part);
+                    for (int c = 0; c < 3; ++c) acc[c] += part[c];
+                }
+    }
+    for (int c = 0; c < 3; ++c) b[(size_t)c * g.Nn + node] = acc[c];
 }
 
 int launch_rhs(const pa_op* op, const double f[3], int face, const double t[3], double* b, const double* d_vert) {
     const Geom g = make_geom(op->mesh, op->p, true);
-    int rc = launch_fill(b, PA_F64, op->N, 0.0, op->stream);
-    if (rc) return rc;
     Mat3 A;
     for (int i = 0; i < 9; ++i) A.a[i] = op->mesh.A[i];
-    const int D = op->p + 1;
-    const long long work = (long long)g.NE * D * D * D;
-    const int nb = (int)((work + 255) / 256);
+    const int nb = (g.Nn + 255) / 256;
     const double tt[3] = {t ? t[0] : 0.0, t ? t[1] : 0.0, t ? t[2] : 0.0};
     hipLaunchKernelGGL(rhs_kernel, dim3(nb), dim3(256), 0, op->stream, b, d_vert, op->d_tab, A, op->p, op->q, g,
                        f ? f[0] : 0.0, f ? f[1] : 0.0, f ? f[2] : 0.0, face, tt[0], tt[1], tt[2]);

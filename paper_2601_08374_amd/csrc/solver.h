@@ -55,8 +55,8 @@ int launch_splitmix(void* v, int dtype, uint64_t seed, int64_t n, hipStream_t s)
 int launch_p_interp_matrix(const double* gll_c, const double* gll_f, int pc, int pf, double* I, hipStream_t s);
 int launch_p_prolong(const void* xc, void* xf, const double* I, int pc, int pf, const Geom& gc, const Geom& gf,
                      int add, int dtype, hipStream_t s);
-int launch_p_restrict(const void* rf, const void* tf, void* rc, const double* I, int pc, int pf, const Geom& gc, const Geom& gf,
-                      int dtype, hipStream_t s);
+int launch_p_restrict(const void* rf, const void* tf, void* rc, void* skr, const double* I, int pc, int pf,
+                      const Geom& gc, const Geom& gf, int dtype, hipStream_t s);
 int launch_h_prolong(const void* xc, void* xf, const HAxis ax[3], const Geom& gc, const Geom& gf, int add, int dtype,
                      hipStream_t s);
 int launch_h_restrict(const void* rf, const void* tf, void* rc, const HAxis ax[3], const Geom& gc, const Geom& gf, int dtype,

@@ -281,107 +281,198 @@ __global__ void vdv_partial_kernel(const T* __restrict__ v, const T* __restrict_
 // A fine node is written only by its owner element (local index < pf, or the last
 // element of the axis), so prolongation is deterministic and race-free.
 // Restriction is the exact transpose: each element contracts the owned entries of
-// the fine vector with I^T and scatter-adds into the coarse vector.
+// the fine vector with I^T; coarse nodes inside the element are written directly and
+// element-boundary ones go to a per-element buffer that p_restrict_gather_kernel sums
+// per coarse node in a fixed order (deterministic, no atomics).
 __device__ __forceinline__ bool owns(int e, int i, int n, int p) { return i < p || e == n - 1; }
 
-template <typename T>
-__global__ void p_prolong_kernel(const T* __restrict__ xc, T* __restrict__ xf, const double* __restrict__ I, int pc,
-                                 int pf, Geom gc, Geom gf, int add) {
-    extern __shared__ double sm[];
-    const int Dc = pc + 1, Df = pf + 1;
-    const int Dc3 = Dc * Dc * Dc;
-    double* X = sm;                         // [3][Dc][Dc][Dc]
-    double* T1 = X + 3 * Dc3;               // [3][Dc][Dc][Df]
-    double* T2 = T1 + 3 * Dc * Dc * Df;     // [3][Dc][Df][Df]
-    double* Is = T2 + 3 * Dc * Df * Df;     // [Df][Dc]
-    const int e = blockIdx.x;
-    const int ex = e % gf.nx, ey = (e / gf.nx) % gf.ny, ez = e / (gf.nx * gf.ny);
-    for (int w = threadIdx.x; w < Df * Dc; w += blockDim.x) Is[w] = I[w];
-    for (int w = threadIdx.x; w < 3 * Dc3; w += blockDim.x) {
-        const int c = w / Dc3, a = w % Dc3;
-        const int ix = a % Dc, iy = (a / Dc) % Dc, iz = a / (Dc * Dc);
-        const int node = (ex * pc + ix) + gc.Nx * ((ey * pc + iy) + gc.Ny * (ez * pc + iz));
+// Element-boundary local nodes of a D^3 element (some index 0 or D-1), numbered in
+// (iz, iy, ix)-lexicographic order: D*D on the full layers iz = 0, D-1 and 4(D-1) on
+// each inner layer.
+__device__ __forceinline__ int skel_count(int D) { return D * D * D - (D - 2) * (D - 2) * (D - 2); }
+__device__ __forceinline__ int skel_slot(int D, int ix, int iy, int iz) {
+    const int P = D - 1, layer = 4 * (D - 1);
+    if (iz == 0) return iy * D + ix;
+    if (iz == P) return D * D + (D - 2) * layer + iy * D + ix;
+    const int base = D * D + (iz - 1) * layer;
+    if (iy == 0) return base + ix;
+    if (iy == P) return base + D + 2 * (D - 2) + ix;
+    return base + D + 2 * (iy - 1) + (ix == P ? 1 : 0);
+}
+
+// Elements per workgroup of the p-transfer kernels: about 256 lanes, one per fine
+// (ix, iy) column of an element.
+constexpr int transfer_elems(int Df) { return 256 / (Df * Df) > 0 ? 256 / (Df * Df) : 1; }
+
+// Prolongation xf (+)= P xc between degrees PF and PC = PF / 2 on one mesh.  The
+// coarse element values are staged in LDS; one lane per fine (ix, iy) column contracts
+// them in x and y for its column, then in z for each fine iz, and writes the nodes of
+// its column that the element owns (clamped fine nodes get 0, or keep their value
+// when adding).
+template <int PF, typename T>
+__global__ void __launch_bounds__(256)
+p_prolong_kernel(const T* __restrict__ xc, T* __restrict__ xf, const double* __restrict__ I, Geom gc, Geom gf,
+                 int add) {
+    constexpr int PC = PF / 2, Dc = PC + 1, Df = PF + 1, Dc3 = Dc * Dc * Dc, EB = transfer_elems(Df);
+    __shared__ double Is[Df * Dc];          // I[i][j] = l^c_j(xi^f_i)
+    __shared__ double X[EB * 3 * Dc3];      // coarse values of the block's elements
+    const int tid = threadIdx.x;
+    const int e0 = blockIdx.x * EB;
+    const int neb = gf.NE - e0 < EB ? gf.NE - e0 : EB;
+    for (int w = tid; w < Df * Dc; w += blockDim.x) Is[w] = I[w];
+    for (int w = tid; w < neb * 3 * Dc3; w += blockDim.x) {
+        const int el = w / (3 * Dc3), r = w % (3 * Dc3), c = r / Dc3, a = r % Dc3;
+        const int e = e0 + el;
+        const int ex = e % gf.nx, ey = (e / gf.nx) % gf.ny, ez = e / (gf.nx * gf.ny);
+        const int jx = a % Dc, jy = (a / Dc) % Dc, jz = a / (Dc * Dc);
+        const size_t node = (size_t)(ex * PC + jx) + gc.Nx * ((ey * PC + jy) + (size_t)gc.Ny * (ez * PC + jz));
         X[w] = (double)xc[(size_t)c * gc.Nn + node];
     }
     __syncthreads();
-    for (int w = threadIdx.x; w < 3 * Dc * Dc * Df; w += blockDim.x) {
-        const int i = w % Df, r = w / Df;   // r = (c, jz, jy)
-        double acc = 0.0;
-        for (int j = 0; j < Dc; ++j) acc += Is[i * Dc + j] * X[r * Dc + j];
-        T1[w] = acc;
+    const int el = tid / (Df * Df), col = tid % (Df * Df);
+    if (el >= neb) return;   // no barrier follows
+    const int ix = col % Df, iy = col / Df;
+    const int e = e0 + el;
+    const int ex = e % gf.nx, ey = (e / gf.nx) % gf.ny, ez = e / (gf.nx * gf.ny);
+    if (!owns(ex, ix, gf.nx, PF) || !owns(ey, iy, gf.ny, PF)) return;
+    const int gx = ex * PF + ix, gy = ey * PF + iy;
+    double Ix[Dc], Iy[Dc];
+#pragma unroll
+    for (int j = 0; j < Dc; ++j) {
+        Ix[j] = Is[ix * Dc + j];
+        Iy[j] = Is[iy * Dc + j];
     }
-    __syncthreads();
-    for (int w = threadIdx.x; w < 3 * Dc * Df * Df; w += blockDim.x) {
-        const int ixf = w % Df, iyf = (w / Df) % Df, r = w / (Df * Df);   // r = (c, jz)
-        double acc = 0.0;
-        for (int j = 0; j < Dc; ++j) acc += Is[iyf * Dc + j] * T1[(r * Dc + j) * Df + ixf];
-        T2[w] = acc;
-    }
-    __syncthreads();
-    const int Df3 = Df * Df * Df;
-    for (int w = threadIdx.x; w < 3 * Df3; w += blockDim.x) {
-        const int c = w / Df3, a = w % Df3;
-        const int ix = a % Df, iy = (a / Df) % Df, iz = a / (Df * Df);
-        if (!owns(ex, ix, gf.nx, pf) || !owns(ey, iy, gf.ny, pf) || !owns(ez, iz, gf.nz, pf)) continue;
-        const int gx = ex * pf + ix, gy = ey * pf + iy, gz = ez * pf + iz;
-        double acc = 0.0;
-        for (int j = 0; j < Dc; ++j) acc += Is[iz * Dc + j] * T2[((c * Dc + j) * Df + iy) * Df + ix];
-        const size_t o = (size_t)c * gf.Nn + gx + gf.Nx * (gy + gf.Ny * gz);
-        if (clamped_node(gf.clamp, gx, gy, gz, gf)) {
-            if (!add) xf[o] = T(0);
-        } else {
-            xf[o] = add ? xf[o] + (T)acc : (T)acc;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double* Xc = X + (el * 3 + c) * Dc3;
+        double Tz[Dc];
+#pragma unroll
+        for (int jz = 0; jz < Dc; ++jz) {
+            double acc = 0.0;
+#pragma unroll
+            for (int jy = 0; jy < Dc; ++jy) {
+                double w = 0.0;
+#pragma unroll
+                for (int jx = 0; jx < Dc; ++jx) w += Ix[jx] * Xc[(jz * Dc + jy) * Dc + jx];
+                acc += Iy[jy] * w;
+            }
+            Tz[jz] = acc;
+        }
+#pragma unroll
+        for (int iz = 0; iz < Df; ++iz) {
+            if (!owns(ez, iz, gf.nz, PF)) continue;
+            const int gz = ez * PF + iz;
+            double v = 0.0;
+#pragma unroll
+            for (int jz = 0; jz < Dc; ++jz) v += Is[iz * Dc + jz] * Tz[jz];
+            const size_t o = (size_t)c * gf.Nn + gx + gf.Nx * (gy + (size_t)gf.Ny * gz);
+            if (clamped_node(gf.clamp, gx, gy, gz, gf)) {
+                if (!add) xf[o] = T(0);
+            } else {
+                xf[o] = add ? xf[o] + (T)v : (T)v;
+            }
         }
     }
 }
 
-template <typename T>
-__global__ void p_restrict_kernel(const T* __restrict__ rf, const T* __restrict__ tf, T* __restrict__ rc,
-                                  const double* __restrict__ I, int pc, int pf, Geom gc, Geom gf) {
-    extern __shared__ double sm[];
-    const int Dc = pc + 1, Df = pf + 1;
-    const int Df3 = Df * Df * Df;
-    double* X = sm;                          // [3][Df][Df][Df] owned fine values
-    double* T1 = X + 3 * Df3;                // [3][Df][Df][Dc]  (z, y fine; x coarse)
-    double* T2 = T1 + 3 * Df * Df * Dc;      // [3][Df][Dc][Dc]
-    double* Is = T2 + 3 * Df * Dc * Dc;      // [Df][Dc]
-    const int e = blockIdx.x;
-    const int ex = e % gf.nx, ey = (e / gf.nx) % gf.ny, ez = e / (gf.nx * gf.ny);
-    for (int w = threadIdx.x; w < Df * Dc; w += blockDim.x) Is[w] = I[w];
-    for (int w = threadIdx.x; w < 3 * Df3; w += blockDim.x) {
-        const int c = w / Df3, a = w % Df3;
-        const int ix = a % Df, iy = (a / Df) % Df, iz = a / (Df * Df);
-        double v = 0.0;
-        if (owns(ex, ix, gf.nx, pf) && owns(ey, iy, gf.ny, pf) && owns(ez, iz, gf.nz, pf)) {
-            const size_t o = (size_t)c * gf.Nn + (ex * pf + ix) + gf.Nx * ((ey * pf + iy) + gf.Ny * (ez * pf + iz));
-            v = tf ? (double)(rf[o] - tf[o]) : (double)rf[o];
+// Restriction rc = P^T (rf - tf) (tf optional), the exact transpose: each element takes
+// the fine values it owns.  Stage 1, one lane per fine (ix, iy) column: contract z into
+// LDS.  Stage 2, one lane per (element, c, jz, jy): contract y and x; coarse nodes inside
+// the element are written directly, element-boundary ones to skr (summed per coarse node
+// in a fixed order by p_restrict_gather_kernel).
+template <int PF, typename T>
+__global__ void __launch_bounds__(256)
+p_restrict_kernel(const T* __restrict__ rf, const T* __restrict__ tf, T* __restrict__ rc, T* __restrict__ skr,
+                  const double* __restrict__ I, Geom gc, Geom gf) {
+    constexpr int PC = PF / 2, Dc = PC + 1, Df = PF + 1, EB = transfer_elems(Df);
+    __shared__ double Is[Df * Dc];
+    __shared__ double U[EB * 3 * Dc * Df * Df];   // [el][c][jz][iy][ix]
+    const int tid = threadIdx.x;
+    const int e0 = blockIdx.x * EB;
+    const int neb = gf.NE - e0 < EB ? gf.NE - e0 : EB;
+    for (int w = tid; w < Df * Dc; w += blockDim.x) Is[w] = I[w];
+    __syncthreads();
+    {
+        const int el = tid / (Df * Df), col = tid % (Df * Df);
+        if (el < neb) {
+            const int ix = col % Df, iy = col / Df;
+            const int e = e0 + el;
+            const int ex = e % gf.nx, ey = (e / gf.nx) % gf.ny, ez = e / (gf.nx * gf.ny);
+            const bool own_xy = owns(ex, ix, gf.nx, PF) && owns(ey, iy, gf.ny, PF);
+            const int gx = ex * PF + ix, gy = ey * PF + iy;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double u[Dc];
+#pragma unroll
+                for (int jz = 0; jz < Dc; ++jz) u[jz] = 0.0;
+#pragma unroll
+                for (int iz = 0; iz < Df; ++iz) {
+                    if (!own_xy || !owns(ez, iz, gf.nz, PF)) continue;
+                    const size_t o = (size_t)c * gf.Nn + gx + gf.Nx * (gy + (size_t)gf.Ny * (ez * PF + iz));
+                    const double v = tf ? (double)(rf[o] - tf[o]) : (double)rf[o];
+#pragma unroll
+                    for (int jz = 0; jz < Dc; ++jz) u[jz] += Is[iz * Dc + jz] * v;
+                }
+#pragma unroll
+                for (int jz = 0; jz < Dc; ++jz) U[((el * 3 + c) * Dc + jz) * Df * Df + col] = u[jz];
+            }
         }
-        X[w] = v;
     }
     __syncthreads();
-    for (int w = threadIdx.x; w < 3 * Df * Df * Dc; w += blockDim.x) {
-        const int j = w % Dc, r = w / Dc;   // r = (c, iz, iy)
-        double acc = 0.0;
-        for (int i = 0; i < Df; ++i) acc += Is[i * Dc + j] * X[r * Df + i];
-        T1[w] = acc;
+    for (int w = tid; w < neb * 3 * Dc * Dc; w += blockDim.x) {
+        const int el = w / (3 * Dc * Dc), r = w % (3 * Dc * Dc), c = r / (Dc * Dc), jz = (r / Dc) % Dc, jy = r % Dc;
+        const double* Ur = U + ((el * 3 + c) * Dc + jz) * Df * Df;
+        double out[Dc];
+#pragma unroll
+        for (int jx = 0; jx < Dc; ++jx) out[jx] = 0.0;
+#pragma unroll 1
+        for (int iy = 0; iy < Df; ++iy) {
+            const double wy = Is[iy * Dc + jy];
+#pragma unroll
+            for (int jx = 0; jx < Dc; ++jx) {
+                double v = 0.0;
+#pragma unroll
+                for (int ix = 0; ix < Df; ++ix) v += Is[ix * Dc + jx] * Ur[iy * Df + ix];
+                out[jx] += wy * v;
+            }
+        }
+        const int e = e0 + el;
+        const int ex = e % gf.nx, ey = (e / gf.nx) % gf.ny, ez = e / (gf.nx * gf.ny);
+#pragma unroll
+        for (int jx = 0; jx < Dc; ++jx) {
+            const bool inner = jx > 0 && jx < PC && jy > 0 && jy < PC && jz > 0 && jz < PC;
+            if (inner) {
+                const int gx = ex * PC + jx, gy = ey * PC + jy, gz = ez * PC + jz;
+                rc[(size_t)c * gc.Nn + gx + gc.Nx * (gy + (size_t)gc.Ny * gz)] = (T)out[jx];
+            } else {
+                skr[((size_t)e * 3 + c) * skel_count(Dc) + skel_slot(Dc, jx, jy, jz)] = (T)out[jx];
+            }
+        }
     }
-    __syncthreads();
-    for (int w = threadIdx.x; w < 3 * Df * Dc * Dc; w += blockDim.x) {
-        const int jx = w % Dc, jy = (w / Dc) % Dc, r = w / (Dc * Dc);   // r = (c, iz)
-        double acc = 0.0;
-        for (int i = 0; i < Df; ++i) acc += Is[i * Dc + jy] * T1[(r * Df + i) * Dc + jx];
-        T2[w] = acc;
-    }
-    __syncthreads();
-    const int Dc3 = Dc * Dc * Dc;
-    for (int w = threadIdx.x; w < 3 * Dc3; w += blockDim.x) {
-        const int c = w / Dc3, a = w % Dc3;
-        const int jx = a % Dc, jy = (a / Dc) % Dc, jz = a / (Dc * Dc);
-        double acc = 0.0;
-        for (int i = 0; i < Df; ++i) acc += Is[i * Dc + jz] * T2[((c * Df + i) * Dc + jy) * Dc + jx];
-        const int gx = ex * pc + jx, gy = ey * pc + jy, gz = ez * pc + jz;
-        if (clamped_node(gc.clamp, gx, gy, gz, gc)) continue;
-        unsafeAtomicAdd(rc + (size_t)c * gc.Nn + gx + gc.Nx * (gy + gc.Ny * gz), (T)acc);
+}
+
+// Every coarse node on an element boundary: the sum of its elements' entries in a fixed
+// (z, y, x) order; clamped nodes get 0.  Element-interior nodes were written already.
+template <typename T>
+__global__ void p_restrict_gather_kernel(T* __restrict__ rc, const T* __restrict__ skr, int pc, Geom gc) {
+    const int Dc = pc + 1, S = skel_count(Dc);
+    GRID_STRIDE(node, (int64_t)gc.Nn) {
+        const int gx = (int)(node % gc.Nx), gy = (int)((node / gc.Nx) % gc.Ny), gz = (int)(node / ((int64_t)gc.Nx * gc.Ny));
+        if (gx % pc != 0 && gy % pc != 0 && gz % pc != 0) continue;   // written by its element
+        const bool cl = clamped_node(gc.clamp, gx, gy, gz, gc);
+        double acc[3] = {0.0, 0.0, 0.0};
+        if (!cl) {
+            const NodeCands nc = node_candidates(gc, pc, gx, gy, gz);
+            for (int kz = 0; kz < 2; ++kz)
+                for (int ky = 0; ky < 2; ++ky)
+                    for (int kx = 0; kx < 2; ++kx) {
+                        if (!(nc.v[0][kx] && nc.v[1][ky] && nc.v[2][kz])) continue;
+                        const int e = nc.e[0][kx] + gc.nx * (nc.e[1][ky] + gc.ny * nc.e[2][kz]);
+                        const int sl = skel_slot(Dc, nc.l[0][kx], nc.l[1][ky], nc.l[2][kz]);
+                        for (int c = 0; c < 3; ++c) acc[c] += (double)skr[((size_t)e * 3 + c) * S + sl];
+                    }
+        }
+        for (int c = 0; c < 3; ++c) rc[(size_t)c * gc.Nn + node] = (T)acc[c];
     }
 }
 
@@ -433,30 +524,30 @@ __global__ void h_prolong_kernel(const T* __restrict__ xc, T* __restrict__ xf, H
 template <typename T>
 __global__ void h_restrict_kernel(const T* __restrict__ rf, const T* __restrict__ tf, T* __restrict__ rc, HAxis ax,
                                   HAxis ay, HAxis az, Geom gc, Geom gf) {
-    GRID_STRIDE(node, (int64_t)gc.Nn) {
+    // one lane per (component, coarse node): the coarse levels are small
+    GRID_STRIDE(w, 3 * (int64_t)gc.Nn) {
+        const int c = (int)(w / gc.Nn);
+        const int64_t node = w % gc.Nn;
         const int jx = (int)(node % gc.Nx), jy = (int)((node / gc.Nx) % gc.Ny), jz = (int)(node / ((int64_t)gc.Nx * gc.Ny));
-        const bool cl = clamped_node(gc.clamp, jx, jy, jz, gc);
-        for (int c = 0; c < 3; ++c) {
-            double acc = 0.0;
-            if (!cl) {
-                for (int a = 0; a < 3; ++a) {
-                    const double wz = az.fw[jz * 3 + a];
-                    if (wz == 0.0) continue;
-                    for (int b = 0; b < 3; ++b) {
-                        const double wy = ay.fw[jy * 3 + b];
-                        if (wy == 0.0) continue;
-                        for (int d = 0; d < 3; ++d) {
-                            const double wx = ax.fw[jx * 3 + d];
-                            if (wx == 0.0) continue;
-                            const size_t o = (size_t)c * gf.Nn + ax.fi[jx * 3 + d] +
-                                             gf.Nx * (ay.fi[jy * 3 + b] + gf.Ny * az.fi[jz * 3 + a]);
-                            acc += wx * wy * wz * (tf ? (double)(rf[o] - tf[o]) : (double)rf[o]);
-                        }
+        double acc = 0.0;
+        if (!clamped_node(gc.clamp, jx, jy, jz, gc)) {
+            for (int a = 0; a < 3; ++a) {
+                const double wz = az.fw[jz * 3 + a];
+                if (wz == 0.0) continue;
+                for (int b = 0; b < 3; ++b) {
+                    const double wy = ay.fw[jy * 3 + b];
+                    if (wy == 0.0) continue;
+                    for (int d = 0; d < 3; ++d) {
+                        const double wx = ax.fw[jx * 3 + d];
+                        if (wx == 0.0) continue;
+                        const size_t o = (size_t)c * gf.Nn + ax.fi[jx * 3 + d] +
+                                         gf.Nx * (ay.fi[jy * 3 + b] + gf.Ny * az.fi[jz * 3 + a]);
+                        acc += wx * wy * wz * (tf ? (double)(rf[o] - tf[o]) : (double)rf[o]);
                     }
                 }
             }
-            rc[(size_t)c * gc.Nn + node] = (T)acc;
         }
+        rc[(size_t)c * gc.Nn + node] = (T)acc;
     }
 }
 
@@ -465,20 +556,14 @@ __global__ void h_restrict_kernel(const T* __restrict__ rf, const T* __restrict_
 // K[(c,a),(d,b)] = detJ lambda P_cd + detJ mu (delta_cd tr P + P_dc), P = J^{-T} M(a,b) J^{-1},
 // M_mn(a,b) = prod over directions of 1D integrals sum_k w_k F(i_a,k) F'(i_b,k), F = G in
 // direction m (resp. n) and B otherwise.  One thread per (element, a, b).
+// Block K_e[(c, a), (d, b)] (c, d = 0..2) of element e for its local nodes a, b.
 template <typename T>
-__global__ void coarse_assemble_kernel(double* __restrict__ A, int N, const T* __restrict__ ed,
-                                       const double* __restrict__ tab, int p, int q, Geom g) {
-    const int D = p + 1, D3 = D * D * D;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long long)g.NE * D3 * D3) return;
-    const int e = (int)(t / ((long long)D3 * D3));
-    const int ab = (int)(t % ((long long)D3 * D3));
-    const int a = ab / D3, b = ab % D3;
+__device__ void coarse_block(const T* __restrict__ ed, const double* __restrict__ tab, int p, int q, int e,
+                             const int (&ia)[3], const int (&ib)[3], double (&K)[3][3]) {
+    const int D = p + 1;
     const double* w = tab + D + q;
     const double* Bt = w + q;
     const double* Gt = Bt + D * q;
-    const int ia[3] = {a % D, (a / D) % D, a / (D * D)};
-    const int ib[3] = {b % D, (b / D) % D, b / (D * D)};
     double M[3][3];
     for (int m = 0; m < 3; ++m)
         for (int n = 0; n < 3; ++n) {
@@ -505,14 +590,39 @@ __global__ void coarse_assemble_kernel(double* __restrict__ A, int N, const T* _
         }
     const double tr = P[0][0] + P[1][1] + P[2][2];
     const double lw = (double)o[9], mw = (double)o[10];
-    const int ex = e % g.nx, ey = (e / g.nx) % g.ny, ez = e / (g.nx * g.ny);
-    const int na = (ex * p + ia[0]) + g.Nx * ((ey * p + ia[1]) + g.Ny * (ez * p + ia[2]));
-    const int nb = (ex * p + ib[0]) + g.Nx * ((ey * p + ib[1]) + g.Ny * (ez * p + ib[2]));
     for (int c = 0; c < 3; ++c)
-        for (int d = 0; d < 3; ++d) {
-            const double v = lw * P[c][d] + mw * ((c == d ? tr : 0.0) + P[d][c]);
-            unsafeAtomicAdd(A + (size_t)(c * g.Nn + na) * N + (d * g.Nn + nb), v);
-        }
+        for (int d = 0; d < 3; ++d) K[c][d] = lw * P[c][d] + mw * ((c == d ? tr : 0.0) + P[d][c]);
+}
+
+// One thread per node pair (na, nb): the blocks of the elements containing both, summed
+// in a fixed order (deterministic, no atomics); pairs sharing no element get 0.
+template <typename T>
+__global__ void coarse_assemble_kernel(double* __restrict__ A, int N, const T* __restrict__ ed,
+                                       const double* __restrict__ tab, int p, int q, Geom g) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)g.Nn * g.Nn) return;
+    const int na = (int)(t / g.Nn), nb = (int)(t % g.Nn);
+    const int ax = na % g.Nx, ay = (na / g.Nx) % g.Ny, az = na / (g.Nx * g.Ny);
+    const int bx = nb % g.Nx, by = (nb / g.Nx) % g.Ny, bz = nb / (g.Nx * g.Ny);
+    double acc[3][3] = {};
+    if (abs(ax - bx) <= p && abs(ay - by) <= p && abs(az - bz) <= p) {
+        const NodeCands nc = node_candidates(g, p, ax, ay, az);
+        for (int kz = 0; kz < 2; ++kz)
+            for (int ky = 0; ky < 2; ++ky)
+                for (int kx = 0; kx < 2; ++kx) {
+                    if (!(nc.v[0][kx] && nc.v[1][ky] && nc.v[2][kz])) continue;
+                    const int ex = nc.e[0][kx], ey = nc.e[1][ky], ez = nc.e[2][kz];
+                    const int ib[3] = {bx - ex * p, by - ey * p, bz - ez * p};
+                    if (ib[0] < 0 || ib[0] > p || ib[1] < 0 || ib[1] > p || ib[2] < 0 || ib[2] > p) continue;
+                    const int ia[3] = {nc.l[0][kx], nc.l[1][ky], nc.l[2][kz]};
+                    double K[3][3];
+                    coarse_block(ed, tab, p, q, ex + g.nx * (ey + g.ny * ez), ia, ib, K);
+                    for (int c = 0; c < 3; ++c)
+                        for (int d = 0; d < 3; ++d) acc[c][d] += K[c][d];
+                }
+    }
+    for (int c = 0; c < 3; ++c)
+        for (int d = 0; d < 3; ++d) A[(size_t)(c * g.Nn + na) * N + (d * g.Nn + nb)] = acc[c][d];
 }
 
 __global__ void coarse_constrain_kernel(double* __restrict__ A, int N, Geom g) {
@@ -772,40 +882,61 @@ int launch_p_interp_matrix(const double* gll_c, const double* gll_f, int pc, int
     return PA_OK;
 }
 
-static size_t p_transfer_lds(int pc, int pf) {
-    const int Dc = pc + 1, Df = pf + 1;
-    const size_t a = 3 * Dc * Dc * Dc + 3 * Dc * Dc * Df + 3 * Dc * Df * Df + Df * Dc;
-    const size_t b = 3 * Df * Df * Df + 3 * Df * Df * Dc + 3 * Df * Dc * Dc + Df * Dc;
-    return (a > b ? a : b) * sizeof(double);
+template <int PF, typename T>
+void p_prolong_launch(const void* xc, void* xf, const double* I, const Geom& gc, const Geom& gf, int add,
+                      hipStream_t s) {
+    constexpr int EB = transfer_elems(PF + 1);
+    const int nb = (gf.NE + EB - 1) / EB;
+    hipLaunchKernelGGL((p_prolong_kernel<PF, T>), dim3(nb), dim3(256), 0, s, cp<T>(xc), mp<T>(xf), I, gc, gf, add);
 }
+
+template <int PF, typename T>
+void p_restrict_launch(const void* rf, const void* tf, void* rc, void* skr, const double* I, const Geom& gc,
+                       const Geom& gf, hipStream_t s) {
+    constexpr int EB = transfer_elems(PF + 1);
+    const int nb = (gf.NE + EB - 1) / EB;
+    hipLaunchKernelGGL((p_restrict_kernel<PF, T>), dim3(nb), dim3(256), 0, s, cp<T>(rf), cp<T>(tf), mp<T>(rc),
+                       mp<T>(skr), I, gc, gf);
+    hipLaunchKernelGGL((p_restrict_gather_kernel<T>), dim3(grid_for(gc.Nn)), dim3(kBlock), 0, s, mp<T>(rc),
+                       cp<T>(skr), PF / 2, gc);
+}
+
+#define PA_PF_SWITCH(pf, CALL)                                                                \
+    switch (pf) {                                                                             \
+        case 2: CALL(2); break;                                                               \
+        case 3: CALL(3); break;                                                               \
+        case 4: CALL(4); break;                                                               \
+        case 5: CALL(5); break;                                                               \
+        case 6: CALL(6); break;                                                               \
+        case 7: CALL(7); break;                                                               \
+        case 8: CALL(8); break;                                                               \
+        default: return fail(PA_EUNSUPPORTED, "p-transfer from degree %d is not built", pf); \
+    }
 
 int launch_p_prolong(const void* xc, void* xf, const double* I, int pc, int pf, const Geom& gc, const Geom& gf,
                      int add, int dtype, hipStream_t s) {
-    const size_t lds = p_transfer_lds(pc, pf);
-    if (dtype == PA_F64)
-        hipLaunchKernelGGL(p_prolong_kernel<double>, dim3(gf.NE), dim3(128), lds, s, cp<double>(xc), mp<double>(xf),
-                           I, pc, pf, gc, gf, add);
-    else
-        hipLaunchKernelGGL(p_prolong_kernel<float>, dim3(gf.NE), dim3(128), lds, s, cp<float>(xc), mp<float>(xf), I,
-                           pc, pf, gc, gf, add);
+    if (pc != pf / 2) return fail(PA_EUNSUPPORTED, "p-transfer %d -> %d: the coarse degree must be %d", pf, pc, pf / 2);
+#define PA_PROLONG(PF)                                                   \
+    if (dtype == PA_F64) p_prolong_launch<PF, double>(xc, xf, I, gc, gf, add, s); \
+    else p_prolong_launch<PF, float>(xc, xf, I, gc, gf, add, s)
+    PA_PF_SWITCH(pf, PA_PROLONG)
+#undef PA_PROLONG
     PA_CHECK_LAUNCH();
     return PA_OK;
 }
 
-int launch_p_restrict(const void* rf, const void* tf, void* rc, const double* I, int pc, int pf, const Geom& gc, const Geom& gf,
-                      int dtype, hipStream_t s) {
-    int rcode = launch_fill(rc, dtype, 3 * (int64_t)gc.Nn, 0.0, s);
-    if (rcode) return rcode;
-    const size_t lds = p_transfer_lds(pc, pf);
-    if (dtype == PA_F64)
-        hipLaunchKernelGGL(p_restrict_kernel<double>, dim3(gf.NE), dim3(128), lds, s, cp<double>(rf), cp<double>(tf), mp<double>(rc),
-                           I, pc, pf, gc, gf);
-    else
-        hipLaunchKernelGGL(p_restrict_kernel<float>, dim3(gf.NE), dim3(128), lds, s, cp<float>(rf), cp<float>(tf), mp<float>(rc), I,
-                           pc, pf, gc, gf);
+int launch_p_restrict(const void* rf, const void* tf, void* rc, void* skr, const double* I, int pc, int pf,
+                      const Geom& gc, const Geom& gf, int dtype, hipStream_t s) {
+    if (pc != pf / 2) return fail(PA_EUNSUPPORTED, "p-transfer %d -> %d: the coarse degree must be %d", pf, pc, pf / 2);
+#define PA_RESTRICT(PF)                                                              \
+    if (dtype == PA_F64) p_restrict_launch<PF, double>(rf, tf, rc, skr, I, gc, gf, s); \
+    else p_restrict_launch<PF, float>(rf, tf, rc, skr, I, gc, gf, s)
+    PA_PF_SWITCH(pf, PA_RESTRICT)
+#undef PA_RESTRICT
     PA_CHECK_LAUNCH();
     return PA_OK;
 }
+#undef PA_PF_SWITCH
 
 int launch_h_prolong(const void* xc, void* xf, const HAxis ax[3], const Geom& gc, const Geom& gf, int add, int dtype,
                      hipStream_t s) {
@@ -822,12 +953,13 @@ int launch_h_prolong(const void* xc, void* xf, const HAxis ax[3], const Geom& gc
 
 int launch_h_restrict(const void* rf, const void* tf, void* rc, const HAxis ax[3], const Geom& gc, const Geom& gf, int dtype,
                       hipStream_t s) {
-    const int g = grid_for(gc.Nn);
+    // 64-lane groups: the coarse levels are small, spread them over more CUs
+    const int g = (int)((3 * (int64_t)gc.Nn + 63) / 64);
     if (dtype == PA_F64)
-        hipLaunchKernelGGL(h_restrict_kernel<double>, dim3(g), dim3(kBlock), 0, s, cp<double>(rf), cp<double>(tf), mp<double>(rc),
+        hipLaunchKernelGGL(h_restrict_kernel<double>, dim3(g), dim3(64), 0, s, cp<double>(rf), cp<double>(tf), mp<double>(rc),
                            ax[0], ax[1], ax[2], gc, gf);
     else
-        hipLaunchKernelGGL(h_restrict_kernel<float>, dim3(g), dim3(kBlock), 0, s, cp<float>(rf), cp<float>(tf), mp<float>(rc), ax[0],
+        hipLaunchKernelGGL(h_restrict_kernel<float>, dim3(g), dim3(64), 0, s, cp<float>(rf), cp<float>(tf), mp<float>(rc), ax[0],
                            ax[1], ax[2], gc, gf);
     PA_CHECK_LAUNCH();
     return PA_OK;
@@ -835,10 +967,7 @@ int launch_h_restrict(const void* rf, const void* tf, void* rc, const HAxis ax[3
 
 int launch_coarse_assemble(double* A, int N, const pa_op* op, hipStream_t s) {
     const Geom g = make_geom(op->mesh, op->p, true);
-    int rc = launch_fill(A, PA_F64, (int64_t)N * N, 0.0, s);
-    if (rc) return rc;
-    const int D3 = (op->p + 1) * (op->p + 1) * (op->p + 1);
-    const long long work = (long long)g.NE * D3 * D3;
+    const long long work = (long long)g.Nn * g.Nn;
     const int nb = (int)((work + 255) / 256);
     if (op->dtype == PA_F64)
         hipLaunchKernelGGL(coarse_assemble_kernel<double>, dim3(nb), dim3(256), 0, s, A, N, cp<double>(op->ed),

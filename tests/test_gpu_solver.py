@@ -268,6 +268,28 @@ def test_small_cantilever_vs_direct(p, mode):
           f"err {_rel(_np(x), u):.2e}")
 
 
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_solve_bitwise_reproducible(mode):
+    """Every reduction of setup and solve runs in a fixed order (no atomics): two solves on
+    freshly built operators and hierarchies give bitwise identical iterates."""
+    pa = _pa()
+    mesh = syn.graded_mesh((6, 3, 2), seed=3, L=(3.0, 1.0, 1.0), clamped_faces=1)
+    NE = mesh.num_elements
+    lam, mu = syn.two_material_lame(NE, seed=4)
+    out = []
+    for _ in range(2):
+        op = pa.Operator(mesh, 4, lam, mu)
+        b = op.rhs((0.1, 0.0, -1.0), 1, (0.0, 0.3, -1.0))
+        d = op.diagonal()
+        x, info, rc = op.solve(b, rtol=1e-9, mode=mode, stop=1, cheb_degree=3, h_levels=1)
+        assert rc == 0
+        out.append((_np(b), _np(d), _np(x), info.iters))
+        op.close()
+    for a, c in zip(out[0][:3], out[1][:3]):
+        assert np.array_equal(a, c)
+    assert out[0][3] == out[1][3]
+
+
 def test_step_api_interleaved_equals_blocking():
     pa = _pa()
     import ctypes as C
