@@ -40,10 +40,10 @@ STEP_PS = (1, 2, 4, 6, 8)
 # source hash of the kernels they were taken on, so an edited kernel reports
 # null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("e8d3ae9104afbc99", 1, "f64"): 336028394,
-    ("e8d3ae9104afbc99", 2, "f64"): 339783546,
-    ("e8d3ae9104afbc99", 4, "f64"): 233080790,
-    ("e8d3ae9104afbc99", 8, "f64"): 178287373,
+    ("bd551d67e5fd8fd9", 1, "f64"): 336064992,
+    ("bd551d67e5fd8fd9", 2, "f64"): 339749760,
+    ("bd551d67e5fd8fd9", 4, "f64"): 233031162,
+    ("bd551d67e5fd8fd9", 8, "f64"): 178275638,
 }
 
 
