@@ -261,11 +261,21 @@ int pa_elast_setup_material(const pa_mesh_t* m, int p, int q, int kind, const do
     // unit Lame parameters: the element data then carries detJ where the kernel needs it
     std::vector<double> one((size_t)NE, 1.0);
     pa_op* op = nullptr;
-    rc = create_op(md, p, q, one.data(), one.data(), dtype, (hipStream_t)hip_stream, &op, false);
+    // p = 1 with per-point Lame data runs in the linear-element kernel (one lane per element),
+    // which reads the data point-major: word k of point alpha of element e at (2 alpha + k) NE + e
+    const bool lin = p == 1 && kind == PA_MAT_QP_ISO;
+    rc = create_op(md, p, q, one.data(), one.data(), dtype, (hipStream_t)hip_stream, &op, lin);
     if (rc) return rc;
     op->mat = kind;
     const size_t words = (size_t)(NE * per);
     const size_t esz = dtype == PA_F64 ? sizeof(double) : sizeof(float);
+    std::vector<double> tr;
+    if (lin) {
+        tr.resize(words);
+        for (int64_t e = 0; e < NE; ++e)
+            for (int64_t w = 0; w < per; ++w) tr[(size_t)(w * NE + e)] = data[e * per + w];
+        data = tr.data();
+    }
     if (hipMalloc(&op->md, words * esz) != hipSuccess) {
         (void)hipGetLastError();
         op->md = nullptr;

@@ -63,10 +63,13 @@ __device__ __forceinline__ size_t lin_slot(int t, int c, int lz, int ly, int lx,
 // g[c][m], pointwise stress and Q = sigma J^{-T} (weights w[qx] * lzy, mzy), and
 // backward X into S0 (G_x channel, summed over qx) and r1, r2 (B_x channels).
 // Inputs per component c and x-column ix: a = B_y B_z x, b = G_y B_z x, e = B_y G_z x.
-template <int Q, typename T>
+// QPM: per-point Lame parameters lq[qx], mq[qx] of the column scale lzy, mzy (which then
+// carry w det J only).
+template <int Q, typename T, bool QPM = false>
 __device__ __forceinline__ void lin_column(const T (&a)[3][2], const T (&b)[3][2], const T (&e)[3][2],
                                            const T (&Ji)[9], const T lzy, const T mzy, const LinTabs<T, Q>& tb,
-                                           T (&S0)[3], T (&r1)[3][2], T (&r2)[3][2]) {
+                                           T (&S0)[3], T (&r1)[3][2], T (&r2)[3][2], const T* lq = nullptr,
+                                           const T* mq = nullptr) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         S0[c] = T(0);
@@ -82,7 +85,8 @@ __device__ __forceinline__ void lin_column(const T (&a)[3][2], const T (&b)[3][2
             g[c][1] = bx0 * b[c][0] + bx1 * b[c][1];
             g[c][2] = bx0 * e[c][0] + bx1 * e[c][1];
         }
-        const T lam = lzy * tb.w[qx], mu = mzy * tb.w[qx];
+        const T lam = QPM ? lzy * tb.w[qx] * lq[qx] : lzy * tb.w[qx];
+        const T mu = QPM ? mzy * tb.w[qx] * mq[qx] : mzy * tb.w[qx];
         T du[3][3];   // du[c][i] = d u_c / d x_i = sum_m Jinv[m][i] g[c][m]
 #pragma unroll
         for (int c = 0; c < 3; ++c)
@@ -117,9 +121,24 @@ __device__ __forceinline__ void lin_column(const T (&a)[3][2], const T (&b)[3][2
 // added to ya (lower face iz = 0) and yb (upper face iz = 1); word k of a face is
 // (c, iy, ix) = (k >> 2, (k >> 1) & 1, k & 1).  Used in single precision, where
 // the lane's state fits two waves per SIMD.
-template <int Q, typename T>
+// Per-point material (QPM): mdp points at the element's (lambda, mu) of point 0; point
+// alpha, word k is mdp[(2 alpha + k) * ns] (point-major layout, elements contiguous).
+template <int Q, typename T, bool QPM>
+__device__ __forceinline__ void lin_point_lame(const T* mdp, size_t ns, int qz, int qy, T (&lq)[Q], T (&mq)[Q]) {
+    if constexpr (QPM) {
+#pragma unroll
+        for (int qx = 0; qx < Q; ++qx) {
+            const size_t al = qx + Q * (qy + Q * qz);
+            lq[qx] = mdp[(2 * al) * ns];
+            mq[qx] = mdp[(2 * al + 1) * ns];
+        }
+    }
+}
+
+template <int Q, typename T, bool QPM = false>
 __device__ __forceinline__ void lin_element_reg(const T (&xa)[12], const T (&xb)[12], const T (&d)[12],
-                                                const LinTabs<T, Q>& tb, T (&ya)[12], T (&yb)[12]) {
+                                                const LinTabs<T, Q>& tb, T (&ya)[12], T (&yb)[12],
+                                                const T* mdp = nullptr, size_t ns = 0) {
     T Ji[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) Ji[k] = d[k];
@@ -153,8 +172,9 @@ __device__ __forceinline__ void lin_element_reg(const T (&xa)[12], const T (&xb)
                     b[c][ix] = z1 - z0;
                     e[c][ix] = by0 * dz[c * 4 + ix] + by1 * dz[c * 4 + 2 + ix];
                 }
-            T S0[3], r1[3][2], r2[3][2];
-            lin_column<Q, T>(a, b, e, Ji, lw * wzy, mw * wzy, tb, S0, r1, r2);
+            T S0[3], r1[3][2], r2[3][2], lq[Q], mq[Q];
+            lin_point_lame<Q, T, QPM>(mdp, ns, qz, qy, lq, mq);
+            lin_column<Q, T, QPM>(a, b, e, Ji, lw * wzy, mw * wzy, tb, S0, r1, r2, lq, mq);
             // backward Y: t0 += B_y (G_x channel) + G_y (channel 1), t2 += B_y (channel 2)
 #pragma unroll
             for (int c = 0; c < 3; ++c)
@@ -194,10 +214,10 @@ constexpr int kLinLds = 256;   // lanes per workgroup = LDS column stride
 // kept live in registers.
 __device__ __forceinline__ void lds_reload_point() { __asm__ volatile("" ::: "memory"); }
 
-template <int Q, typename T>
+template <int Q, typename T, bool QPM = false>
 __device__ __forceinline__ void lin_element_lds(const T* __restrict__ xa, const T* __restrict__ xb,
                                                 const T (&d)[12], const LinTabs<T, Q>& tb, T (&ya)[12],
-                                                T (&yb)[12]) {
+                                                T (&yb)[12], const T* mdp = nullptr, size_t ns = 0) {
     constexpr int S = kLinLds;
     T Ji[9];
 #pragma unroll
@@ -223,8 +243,9 @@ __device__ __forceinline__ void lin_element_lds(const T* __restrict__ xa, const 
                     b[c][ix] = z1 - z0;
                     e[c][ix] = by0 * (b0 - a0) + by1 * (b1 - a1);
                 }
-            T S0[3], r1[3][2], r2[3][2];
-            lin_column<Q, T>(a, b, e, Ji, lw * wzy, mw * wzy, tb, S0, r1, r2);
+            T S0[3], r1[3][2], r2[3][2], lq[Q], mq[Q];
+            lin_point_lame<Q, T, QPM>(mdp, ns, qz, qy, lq, mq);
+            lin_column<Q, T, QPM>(a, b, e, Ji, lw * wzy, mw * wzy, tb, S0, r1, r2, lq, mq);
             // backward Y and Z into the faces: t0 = B_y (G_x channel) + G_y (channel 1)
             // takes B_z, t2 = B_y (channel 2) takes G_z = (-1, +1)
 #pragma unroll
@@ -248,10 +269,10 @@ __device__ __forceinline__ void lin_element_lds(const T* __restrict__ xa, const 
 template <typename T>
 constexpr bool kLinXInLds = sizeof(T) == 8;
 
-template <int Q, typename T>
+template <int Q, typename T, bool QPM = false>
 __global__ void __launch_bounds__(256)
 pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, const T* __restrict__ ed,
-                    const LinTabs<T, Q> tb, const Geom g, const int TZ, const int add) {
+                    const LinTabs<T, Q> tb, const Geom g, const int TZ, const int add, const T* __restrict__ md) {
     constexpr int TX = kLinTX, TY = kLinTY;
     static_assert(TX * TY == 64 && kLinLds == 256, "one tile per wavefront, four per workgroup");
     const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + TZ - 1) / TZ;
@@ -331,6 +352,12 @@ pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ 
             }
     };
 
+    // per-point material of element (ex, ey, ez); lanes past the mesh read element 0 (their
+    // element data is zero)
+    auto mat_ptr = [&](int ez) -> const T* {
+        if constexpr (QPM) return md + (valid ? (size_t)(ex + g.nx * (ey + g.ny * ez)) : (size_t)0);
+        else return nullptr;
+    };
     T xn[12], dn[12], ya[12];
     auto to_face = [](const T (&f)[12], T (&v)[3][2][2]) {
 #pragma unroll
@@ -361,7 +388,8 @@ pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ 
                 d[k] = dn[k];
                 yb[k] = T(0);
             }
-            lin_element_lds<Q, T>(col + 12 * fa * kLinLds, col + 12 * (1 - fa) * kLinLds, d, tb, ya, yb);
+            lin_element_lds<Q, T, QPM>(col + 12 * fa * kLinLds, col + 12 * (1 - fa) * kLinLds, d, tb, ya, yb,
+                                       mat_ptr(ez), (size_t)g.NE);
             if (ez + 1 < ez1) {
                 load_face(ez + 2, xn);
                 load_data(ez + 1, dn);
@@ -392,7 +420,7 @@ pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ 
                 load_face(ez + 2, xn);
                 load_data(ez + 1, dn);
             }
-            lin_element_reg<Q, T>(xa, xb, d, tb, ya, yb);
+            lin_element_reg<Q, T, QPM>(xa, xb, d, tb, ya, yb, mat_ptr(ez), (size_t)g.NE);
             T v[3][2][2];
             to_face(ya, v);
             emit_layer(v, ez);
@@ -462,7 +490,7 @@ pa_lin_skeleton_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __re
     }
 }
 
-template <int Q, typename T>
+template <int Q, typename T, bool QPM = false>
 int launch_lin(const ApplyLaunch& L) {
     const Geom& g = L.g;
     if (g.NE == 0) return PA_OK;
@@ -479,8 +507,8 @@ int launch_lin(const ApplyLaunch& L) {
     const int tz = lin_chunk(n);
     const int64_t nt = lin_tiles(n, tz);
     const int nb = (int)((nt + 3) / 4);
-    hipLaunchKernelGGL((pa_apply_lin_kernel<Q, T>), dim3(nb), dim3(256), 0, L.stream, (const T*)L.x, (T*)L.y,
-                       (T*)L.sk, (const T*)L.ed, tb, g, tz, L.add);
+    hipLaunchKernelGGL((pa_apply_lin_kernel<Q, T, QPM>), dim3(nb), dim3(256), 0, L.stream, (const T*)L.x, (T*)L.y,
+                       (T*)L.sk, (const T*)L.ed, tb, g, tz, L.add, (const T*)L.md);
     PA_HIP(hipGetLastError());
     const int nb2 = (g.Nn + 255) / 256;
     hipLaunchKernelGGL((pa_lin_skeleton_kernel<T>), dim3(nb2), dim3(256), 0, L.stream, (const T*)L.x, (T*)L.y,
@@ -490,9 +518,15 @@ int launch_lin(const ApplyLaunch& L) {
 }
 
 int launch_apply_p1(const ApplyLaunch& L, int q_off, int dtype) {
-    // general material data and non-affine geometry go through the sum-factorized kernel
+    // per-point Lame data stays in this kernel (point-major layout, see pa_elast_setup_material);
+    // the anisotropic stiffness, non-affine geometry and unstructured meshes go through the
+    // sum-factorized kernel
     if (L.kmap) return launch_apply_unstructured<1>(L, q_off, dtype);
     if (L.geo != PA_GEOM_AFFINE) return launch_apply_geometry<1>(L, q_off, dtype);
+    if (L.mat == PA_MAT_QP_ISO) {
+        if (q_off != 1) return fail(PA_EUNSUPPORTED, "general material data is built for q = p + 2 only");
+        return dtype == PA_F64 ? launch_lin<3, double, true>(L) : launch_lin<3, float, true>(L);
+    }
     if (L.mat != PA_MAT_ELEM_ISO) return launch_apply_material<1>(L, q_off, dtype);
     if (dtype == PA_F64) {
         switch (q_off) {
