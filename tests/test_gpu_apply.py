@@ -311,3 +311,23 @@ def test_apply_variant_errors():
     # the fused variant is the production apply
     xr = torch.tensor(syn.uniform_vector(op4.N, 3), dtype=torch.float64, device="cuda")
     assert torch.equal(op4.apply_variant(xr, variant=pa.capi.PA_VARIANT_FUSED), op4.apply(xr))
+
+
+def test_fma_probe():
+    """The measurement probe: argument checks and one finite value per lane."""
+    import ctypes as C
+    pa = _pa()
+    capi = pa.capi
+    blocks = 8
+    for dtype, tdt in ((capi.PA_F64, torch.float64), (capi.PA_F32, torch.float32)):
+        out = torch.full((blocks * 256,), float("nan"), dtype=tdt, device="cuda")
+        stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        assert capi.pa_probe_fma(C.c_void_p(out.data_ptr()), dtype, blocks, 64, stream) == capi.PA_OK
+        torch.cuda.synchronize()
+        assert bool(torch.isfinite(out).all())
+    buf = torch.empty(256, dtype=torch.float64, device="cuda")
+    ptr = C.c_void_p(buf.data_ptr())
+    assert capi.pa_probe_fma(None, capi.PA_F64, 1, 1, None) == capi.PA_EINVAL
+    assert capi.pa_probe_fma(ptr, 7, 1, 1, None) == capi.PA_EINVAL
+    assert capi.pa_probe_fma(ptr, capi.PA_F64, 0, 1, None) == capi.PA_EINVAL
+    assert capi.pa_probe_fma(ptr, capi.PA_F64, 1, 0, None) == capi.PA_EINVAL
