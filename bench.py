@@ -40,10 +40,10 @@ STEP_PS = (1, 2, 4, 6, 8)
 # source hash of the kernels they were taken on, so an edited kernel reports
 # null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("bd551d67e5fd8fd9", 1, "f64"): 336064992,
-    ("bd551d67e5fd8fd9", 2, "f64"): 339749760,
-    ("bd551d67e5fd8fd9", 4, "f64"): 233031162,
-    ("bd551d67e5fd8fd9", 8, "f64"): 178275638,
+    ("10900d7518a3d1d7", 1, "f64"): 336033008,
+    ("10900d7518a3d1d7", 2, "f64"): 339796970,
+    ("10900d7518a3d1d7", 4, "f64"): 233249152,
+    ("10900d7518a3d1d7", 8, "f64"): 178304150,
 }
 
 
