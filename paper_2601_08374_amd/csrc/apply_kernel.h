@@ -198,6 +198,16 @@ struct Skel {
     __host__ __device__ __forceinline__ static bool interior(int ix, int iy, int iz) {
         return ix > 0 && ix < P && iy > 0 && iy < P && iz > 0 && iz < P;
     }
+    // A row (iy, iz) is either entirely on the element boundary ("full": its nodes have
+    // consecutive slots from index(0, iy, iz)) or crosses the interior (only its two end
+    // nodes are skeleton nodes, at index(0, iy, iz) and index(0, iy, iz) + 1).
+    __host__ __device__ __forceinline__ static bool full_row(int iy, int iz) {
+        return iy == 0 || iy == P || iz == 0 || iz == P;
+    }
+    // Slot of node ix of a row from the row's first slot; not called for interior nodes.
+    __host__ __device__ __forceinline__ static int row_slot(int s0, bool full, int ix) {
+        return full ? s0 + ix : s0 + (ix == P ? 1 : 0);
+    }
     // Buffer layout: node-major ([c][s][e]) up to p = 5, so that the skeleton kernel's
     // reads of one slot for consecutive elements are contiguous; element-major
     // ([e][c][s]) from p = 6 on, where an element's slots are many and its face rows
@@ -368,17 +378,22 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
     constexpr int GX = (NL + NT - 1) / NT;
     static_assert(GX * D <= 32, "clamp mask bits");
     int ln_node[GX];       // global node of (ix = 0) of the line, or -1
+    int ln_slot[GX];       // skeleton slot of (ix = 0) of the line
+    unsigned ln_full = 0u; // bit j: the line lies on the element boundary
     unsigned ln_cl = 0u;   // bit j*D + ix: clamped node (read as 0)
     int ln_nodes[UNS ? GX : 1][UNS ? D : 1];   // unstructured: every node of the line
     __syncthreads();       // ebase, ecoord, Es ready
 #pragma unroll
     for (int j = 0; j < GX; ++j) {
         ln_node[j] = -1;
+        ln_slot[j] = 0;
         const int l = tid + j * NT;
         if (l < NL) {
             const int el = l / (D * D), r = l % (D * D);
             const int iz = r / D, iy = r % D;
             const int b = ebase[el];
+            ln_slot[j] = SK::index(0, iy, iz);
+            if (SK::full_row(iy, iz)) ln_full |= 1u << j;
             if (UNS && b >= 0) {
                 ln_node[j] = 0;
                 const int* mp = kmap + (size_t)(e0 + el) * (D * D * D) + D * (iy + D * iz);
@@ -636,22 +651,26 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
 #pragma unroll
                 for (int k = 0; k < Q; ++k) { a0[k] = ri[k]; a1[k] = ri[UC + k]; }
                 eo_contract2<-1, 1>(a0, tab.Gt, a1, tab.Bt, yo);
+                const bool full = (ln_full >> j) & 1u;
 #pragma unroll
                 for (int ix = 0; ix < D; ++ix) {
+                    // the end nodes of a row are always skeleton nodes
+                    const bool inner = ix > 0 && ix < P && !full;
                     if constexpr (UNS) {
-                        if (SK::interior(ix, iy, iz)) {
+                        if (inner) {
                             // sole owner; a clamped interior node keeps its input in a constrained apply
                             const size_t o = c * NN + ln_nodes[j][ix];
                             const T v = ((ln_cl >> (j * D + ix)) & 1u) ? x[o] : yo[ix];
                             y[o] = add ? y[o] + v : v;
                         } else {
-                            sk[(size_t)kpos[(size_t)(e0 + el) * SK::S + SK::index(ix, iy, iz)] * 3 + c] = yo[ix];
+                            sk[(size_t)kpos[(size_t)(e0 + el) * SK::S + SK::row_slot(ln_slot[j], full, ix)] * 3 + c] =
+                                yo[ix];
                         }
-                    } else if (SK::interior(ix, iy, iz)) {
+                    } else if (inner) {
                         T* yp = y + c * NN + ln_node[j] + ix;
                         *yp = add ? *yp + yo[ix] : yo[ix];
                     } else {
-                        sk[SK::offset(e0 + el, c, SK::index(ix, iy, iz), g.NE)] = yo[ix];
+                        sk[SK::offset(e0 + el, c, SK::row_slot(ln_slot[j], full, ix), g.NE)] = yo[ix];
                     }
                 }
             }
