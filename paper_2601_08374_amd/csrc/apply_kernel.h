@@ -127,16 +127,66 @@ __device__ __forceinline__ void eo_contract(const T (&in)[NI], T (&out)[NO], con
     }
 }
 
-// Two operators applied to two inputs and summed: out = in1 M1 + in2 M2.
-template <int S1, int S2, typename T, int NI, int NO, class TAB>
-__device__ __forceinline__ void eo_contract2(const T (&in1)[NI], const TAB& t1, const T (&in2)[NI], const TAB& t2,
-                                             T (&out)[NO]) {
-    eo_contract<S1, false>(in1, out, t1);
-    eo_contract<S2, true>(in2, out, t2);
+// Backward (quadrature -> nodal) contraction with the forward even-odd table F of the
+// same 1D matrix M (D x Q), read transposed: out[i] = sum_k in[k] M[i][k].  With
+// s[k] = in[k] + in[Q-1-k], a[k] = in[k] - in[Q-1-k] (s of the middle point = its input)
+// and the symmetry M[D-1-i][Q-1-k] = SIGN M[i][k], the pair i, D-1-i is
+//   SIGN > 0: S = sum_k s[k] P[i][k], A = sum_k a[k] N[i][k]; out = S + A, S - A
+//   SIGN < 0: S = sum_k s[k] N[i][k], A = sum_k a[k] P[i][k]; out = A + S, A - S
+// and an odd D's middle output is the S (SIGN > 0) or A (SIGN < 0) sum alone.  These
+// are the numbers of the even-odd form of M^T, so the backward sweeps need no table of
+// their own (half the scalar registers the tables take).
+template <typename T, int NI, int NO>   // NI = Q inputs, NO = D outputs
+struct EOT {
+    const EOTab<T, NO, NI>& f;
+};
+
+template <int SIGN, bool ADD, typename T, int NI, int NO>
+__device__ __forceinline__ void eo_contract(const T (&in)[NI], T (&out)[NO], const EOT<T, NI, NO> tt) {
+    using F = EOTab<T, NO, NI>;
+    constexpr int hD = F::hI, mD = F::mI, hQ = F::hO, mQ = F::mO, KQ = F::KO;
+    const F& t = tt.f;
+    T s[KQ], a[hQ > 0 ? hQ : 1];
+#pragma unroll
+    for (int k = 0; k < hQ; ++k) {
+        s[k] = in[k] + in[NI - 1 - k];
+        a[k] = in[k] - in[NI - 1 - k];
+    }
+    if (mQ) s[hQ] = in[hQ];
+#pragma unroll
+    for (int i = 0; i < hD + mD; ++i) {
+        const bool mid = mD && i == hD;
+        T S = T(0), A = T(0);
+        if (SIGN > 0) {
+#pragma unroll
+            for (int k = 0; k < KQ; ++k) S = fma(s[k], t.P[i * KQ + k], S);
+            if (!mid) {
+#pragma unroll
+                for (int k = 0; k < hQ; ++k) A = fma(a[k], t.N[i * KQ + k], A);
+            }
+        } else {
+            if (!mid) {
+#pragma unroll
+                for (int k = 0; k < KQ; ++k) S = fma(s[k], t.N[i * KQ + k], S);
+            }
+#pragma unroll
+            for (int k = 0; k < hQ; ++k) A = fma(a[k], t.P[i * KQ + k], A);
+        }
+        const T ev = SIGN > 0 ? S : A, od = SIGN > 0 ? A : S;
+        if (mid) {
+            if (ADD) out[i] += ev; else out[i] = ev;
+        } else {
+            if (ADD) { out[i] += ev + od; out[NO - 1 - i] += ev - od; }
+            else { out[i] = ev + od; out[NO - 1 - i] = ev - od; }
+        }
+    }
 }
 
 // Even-odd tables from p = 4 on (D >= 5); plain tables below.
-template <typename T, int NI, int NO, bool EO = (NI >= 5 && NO >= 5)>
+template <int NI, int NO>
+constexpr bool kEvenOdd = NI >= 5 && NO >= 5;
+
+template <typename T, int NI, int NO, bool EO = kEvenOdd<NI, NO>>
 struct TabSel {
     using type = EOTab<T, NI, NO>;
     static void fill(type& t, const double* M) { fill_eo<T, NI, NO>(t, M); }
@@ -147,27 +197,50 @@ struct TabSel<T, NI, NO, false> {
     static void fill(type& t, const double* M) { fill_direct<T, NI, NO>(t, M); }
 };
 
+// Backward tables: plain transposed tables below p = 4; none in the even-odd range,
+// where the backward sweeps read the forward tables transposed (EOT).
+template <typename T, int D, int Q, bool EO = kEvenOdd<D, Q>>
+struct BackTabs {
+    typename TabSel<T, Q, D>::type Bt, Gt;   // quadrature (Q) -> nodal (D)
+};
+template <typename T, int D, int Q>
+struct BackTabs<T, D, Q, true> {};
+
 template <typename T, int D, int Q>
 struct ApplyTabs {
     typename TabSel<T, D, Q>::type Bf, Gf;   // forward: nodal (D) -> quadrature (Q)
-    typename TabSel<T, Q, D>::type Bt, Gt;   // backward: quadrature (Q) -> nodal (D)
+    BackTabs<T, D, Q> bk;
     T w[Q];
     T x[Q];   // Gauss-Legendre points on [0,1] (trilinear geometry)
 };
 
+// Backward operands B^T and G^T of the apply tables.
+template <typename T, int D, int Q>
+__device__ __forceinline__ decltype(auto) back_B(const ApplyTabs<T, D, Q>& t) {
+    if constexpr (kEvenOdd<D, Q>) return EOT<T, Q, D>{t.Bf};
+    else return (t.bk.Bt);
+}
+template <typename T, int D, int Q>
+__device__ __forceinline__ decltype(auto) back_G(const ApplyTabs<T, D, Q>& t) {
+    if constexpr (kEvenOdd<D, Q>) return EOT<T, Q, D>{t.Gf};
+    else return (t.bk.Gt);
+}
+
 template <typename T, int D, int Q>
 inline ApplyTabs<T, D, Q> make_tabs(const Tables& t) {
     ApplyTabs<T, D, Q> r;
-    double Bt[D * Q], Gt[D * Q];
-    for (int i = 0; i < D; ++i)
-        for (int k = 0; k < Q; ++k) {
-            Bt[k * D + i] = t.B[i * Q + k];
-            Gt[k * D + i] = t.G[i * Q + k];
-        }
     TabSel<T, D, Q>::fill(r.Bf, t.B);
     TabSel<T, D, Q>::fill(r.Gf, t.G);
-    TabSel<T, Q, D>::fill(r.Bt, Bt);
-    TabSel<T, Q, D>::fill(r.Gt, Gt);
+    if constexpr (!kEvenOdd<D, Q>) {
+        double Bt[D * Q], Gt[D * Q];
+        for (int i = 0; i < D; ++i)
+            for (int k = 0; k < Q; ++k) {
+                Bt[k * D + i] = t.B[i * Q + k];
+                Gt[k * D + i] = t.G[i * Q + k];
+            }
+        TabSel<T, Q, D>::fill(r.bk.Bt, Bt);
+        TabSel<T, Q, D>::fill(r.bk.Gt, Gt);
+    }
     for (int k = 0; k < Q; ++k) r.w[k] = (T)t.w[k];
     for (int k = 0; k < Q; ++k) r.x[k] = (T)t.xq[k];
     return r;
@@ -604,9 +677,9 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
         // reading Ra before the barrier that preceded the previous X sweep)
         if (has_col) {
             T t0[D], t1[D], t2[D];
-            eo_contract<1, false>(gq[c][0], t0, tab.Bt);
-            eo_contract<1, false>(gq[c][1], t1, tab.Bt);
-            eo_contract<-1, false>(gq[c][2], t2, tab.Gt);
+            eo_contract<1, false>(gq[c][0], t0, back_B(tab));
+            eo_contract<1, false>(gq[c][1], t1, back_B(tab));
+            eo_contract<-1, false>(gq[c][2], t2, back_G(tab));
             T* so = Ra + cel * ST + cqy * RY + cqx;
 #pragma unroll
             for (int i = 0; i < D; ++i) {
@@ -628,8 +701,9 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
                 a1[k] = ti[RC + k * RY];
                 a2[k] = ti[2 * RC + k * RY];
             }
-            eo_contract<1, false>(a0, r0, tab.Bt);
-            eo_contract2<-1, 1>(a1, tab.Gt, a2, tab.Bt, r12);
+            eo_contract<1, false>(a0, r0, back_B(tab));
+            eo_contract<-1, false>(a1, r12, back_G(tab));
+            eo_contract<1, true>(a2, r12, back_B(tab));
             T* ro = Ua + el * UT + iz * UZ + qx;
 #pragma unroll
             for (int i = 0; i < D; ++i) {
@@ -650,7 +724,8 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
                 T a0[Q], a1[Q], yo[D];
 #pragma unroll
                 for (int k = 0; k < Q; ++k) { a0[k] = ri[k]; a1[k] = ri[UC + k]; }
-                eo_contract2<-1, 1>(a0, tab.Gt, a1, tab.Bt, yo);
+                eo_contract<-1, false>(a0, yo, back_G(tab));
+                eo_contract<1, true>(a1, yo, back_B(tab));
                 const bool full = (ln_full >> j) & 1u;
 #pragma unroll
                 for (int ix = 0; ix < D; ++ix) {
