@@ -121,6 +121,39 @@ class GeneralOperator:
             y[self.ess] = x_in[self.ess]
         return y
 
+    def element_matrix(self, e: int) -> np.ndarray:
+        """K^e = sum_alpha w_alpha detJ B_alpha^T C_V(alpha) B_alpha ([3 D^3, 3 D^3])."""
+        for els, B, W in self.groups:
+            k = np.searchsorted(els, e)
+            if k < len(els) and els[k] == e:
+                return np.einsum("a,akn,akl,alm->nm", W, B, self.C[e], B)
+        raise IndexError(e)
+
+    def dense(self, constrained: bool = False) -> np.ndarray:
+        """Assembled dense matrix (small problems only); constrained: identity on the
+        clamped rows and columns."""
+        A = np.zeros((self.N, self.N))
+        for els, B, W in self.groups:
+            for e in els:
+                d = self.edofs[e]
+                A[np.ix_(d, d)] += np.einsum("a,akn,akl,alm->nm", W, B, self.C[e], B)
+        if constrained:
+            A[self.ess, :] = 0.0
+            A[:, self.ess] = 0.0
+            A[self.ess, self.ess] = 1.0
+        return A
+
+    def diagonal(self, constrained: bool = False) -> np.ndarray:
+        """diag(A): per element, K^e_nn = sum_alpha w detJ sum_kl B_akn C_akl B_aln."""
+        d = np.zeros(self.N)
+        for els, B, W in self.groups:
+            dofs = self.edofs[els]
+            DE = np.einsum("a,akn,eakl,aln->en", W, B, self.C[els], B)
+            d += np.bincount(dofs.ravel(), DE.ravel(), minlength=self.N)
+        if constrained:
+            d[self.ess] = 1.0
+        return d
+
     def energy_of_affine(self, E: np.ndarray) -> float:
         """(1/2) sum_e sum_alpha w detJ eps_V^T C_V eps_V for u(X) = E X (constant strain)."""
         eps = 0.5 * (E + E.T)
