@@ -126,8 +126,15 @@ class GeneralOperator:
         for els, B, W in self.groups:
             k = np.searchsorted(els, e)
             if k < len(els) and els[k] == e:
-                return np.einsum("a,akn,akl,alm->nm", W, B, self.C[e], B)
+                return self._element_matrix(B, W, self.C[e])
         raise IndexError(e)
+
+    @staticmethod
+    def _element_matrix(B, W, C):
+        # sum over points alpha and Voigt rows k of (W B)_akn (C B)_akm, as one matrix product
+        CB = np.einsum("akl,alm->akm", C, B)
+        nk = B.shape[0] * B.shape[1]
+        return (B * W[:, None, None]).reshape(nk, -1).T @ CB.reshape(nk, -1)
 
     def dense(self, constrained: bool = False) -> np.ndarray:
         """Assembled dense matrix (small problems only); constrained: identity on the
@@ -136,7 +143,7 @@ class GeneralOperator:
         for els, B, W in self.groups:
             for e in els:
                 d = self.edofs[e]
-                A[np.ix_(d, d)] += np.einsum("a,akn,akl,alm->nm", W, B, self.C[e], B)
+                A[np.ix_(d, d)] += self._element_matrix(B, W, self.C[e])
         if constrained:
             A[self.ess, :] = 0.0
             A[:, self.ess] = 0.0
@@ -148,7 +155,8 @@ class GeneralOperator:
         d = np.zeros(self.N)
         for els, B, W in self.groups:
             dofs = self.edofs[els]
-            DE = np.einsum("a,akn,eakl,aln->en", W, B, self.C[els], B)
+            DE = np.stack([np.einsum("akn,akn->n", B * W[:, None, None], np.einsum("akl,aln->akn", self.C[e], B))
+                           for e in els])
             d += np.bincount(dofs.ravel(), DE.ravel(), minlength=self.N)
         if constrained:
             d[self.ess] = 1.0
