@@ -202,6 +202,71 @@ int apply_op(const pa_op* op, const void* x, void* y, int flags) {
     return fail(PA_EUNSUPPORTED, "p = %d not built", op->p);
 }
 
+int create_material_op(const MeshDesc& md, int p, int q, int kind, const double* data, int dtype, hipStream_t s,
+                       pa_op** out) {
+    const int64_t NE = (int64_t)md.n[0] * md.n[1] * md.n[2];
+    const int64_t Q3 = (int64_t)q * q * q;
+    const int64_t per = kind == PA_MAT_QP_ISO ? 2 * Q3 : 21;
+    // unit Lame parameters: the element data then carries detJ where the kernel needs it
+    std::vector<double> one((size_t)NE, 1.0);
+    pa_op* op = nullptr;
+    // p = 1 with per-point Lame data runs in the linear-element kernel (one lane per element),
+    // which reads the data point-major: word k of point alpha of element e at (2 alpha + k) NE + e
+    const bool lin = p == 1 && kind == PA_MAT_QP_ISO;
+    int rc = create_op(md, p, q, one.data(), one.data(), dtype, s, &op, lin);
+    if (rc) return rc;
+    op->mat = kind;
+    op->md_point_major = lin;
+    if (kind == PA_MAT_QP_ISO) {
+        // kept for solver hierarchies: the data itself (level operators in another precision)
+        // and its quadrature-weighted element means (the coarse levels' per-element parameters)
+        op->mdata.assign(data, data + NE * per);
+        for (int64_t e = 0; e < NE; ++e) {
+            double sl = 0.0, sm = 0.0, sw = 0.0;
+            for (int kz = 0; kz < q; ++kz)
+                for (int ky = 0; ky < q; ++ky)
+                    for (int kx = 0; kx < q; ++kx) {
+                        const double w = op->tab.w[kx] * op->tab.w[ky] * op->tab.w[kz];
+                        const int64_t al = kx + q * (ky + (int64_t)q * kz);
+                        sl += w * data[(e * Q3 + al) * 2];
+                        sm += w * data[(e * Q3 + al) * 2 + 1];
+                        sw += w;
+                    }
+            op->lam[e] = sl / sw;
+            op->mu[e] = sm / sw;
+        }
+    }
+    const size_t words = (size_t)(NE * per);
+    const size_t esz = dtype == PA_F64 ? sizeof(double) : sizeof(float);
+    std::vector<double> tr;
+    if (lin) {
+        tr.resize(words);
+        for (int64_t e = 0; e < NE; ++e)
+            for (int64_t w = 0; w < per; ++w) tr[(size_t)(w * NE + e)] = data[e * per + w];
+        data = tr.data();
+    }
+    if (hipMalloc(&op->md, words * esz) != hipSuccess) {
+        (void)hipGetLastError();
+        op->md = nullptr;
+        pa_elast_destroy(op);
+        return fail(PA_ENOMEM, "device allocation of the material data failed");
+    }
+    hipError_t e;
+    if (dtype == PA_F64) {
+        e = hipMemcpy(op->md, data, words * esz, hipMemcpyHostToDevice);
+    } else {
+        std::vector<float> f(words);
+        for (size_t i = 0; i < words; ++i) f[i] = (float)data[i];
+        e = hipMemcpy(op->md, f.data(), words * esz, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        pa_elast_destroy(op);
+        return fail(PA_EHIP, "material upload failed: %s", hipGetErrorString(e));
+    }
+    *out = op;
+    return PA_OK;
+}
+
 }  // namespace pa
 
 using namespace pa;
@@ -258,44 +323,7 @@ int pa_elast_setup_material(const pa_mesh_t* m, int p, int q, int kind, const do
     const int64_t per = kind == PA_MAT_QP_ISO ? 2 * (int64_t)q * q * q : 21;
     rc = check_material(kind, data, NE, per);
     if (rc) return rc;
-    // unit Lame parameters: the element data then carries detJ where the kernel needs it
-    std::vector<double> one((size_t)NE, 1.0);
-    pa_op* op = nullptr;
-    // p = 1 with per-point Lame data runs in the linear-element kernel (one lane per element),
-    // which reads the data point-major: word k of point alpha of element e at (2 alpha + k) NE + e
-    const bool lin = p == 1 && kind == PA_MAT_QP_ISO;
-    rc = create_op(md, p, q, one.data(), one.data(), dtype, (hipStream_t)hip_stream, &op, lin);
-    if (rc) return rc;
-    op->mat = kind;
-    const size_t words = (size_t)(NE * per);
-    const size_t esz = dtype == PA_F64 ? sizeof(double) : sizeof(float);
-    std::vector<double> tr;
-    if (lin) {
-        tr.resize(words);
-        for (int64_t e = 0; e < NE; ++e)
-            for (int64_t w = 0; w < per; ++w) tr[(size_t)(w * NE + e)] = data[e * per + w];
-        data = tr.data();
-    }
-    if (hipMalloc(&op->md, words * esz) != hipSuccess) {
-        (void)hipGetLastError();
-        op->md = nullptr;
-        pa_elast_destroy(op);
-        return fail(PA_ENOMEM, "device allocation of the material data failed");
-    }
-    hipError_t e;
-    if (dtype == PA_F64) {
-        e = hipMemcpy(op->md, data, words * esz, hipMemcpyHostToDevice);
-    } else {
-        std::vector<float> f(words);
-        for (size_t i = 0; i < words; ++i) f[i] = (float)data[i];
-        e = hipMemcpy(op->md, f.data(), words * esz, hipMemcpyHostToDevice);
-    }
-    if (e != hipSuccess) {
-        pa_elast_destroy(op);
-        return fail(PA_EHIP, "material upload failed: %s", hipGetErrorString(e));
-    }
-    *out = op;
-    return PA_OK;
+    return create_material_op(md, p, q, kind, data, dtype, (hipStream_t)hip_stream, out);
 }
 
 void pa_elast_destroy(pa_op_t* op) {
@@ -337,8 +365,6 @@ int pa_elast_apply(pa_op_t* op, const void* x, void* y) { return pa_elast_apply_
 int pa_elast_diagonal(pa_op_t* op, void* d, int flags) {
     if (!op || !d) return fail(PA_EINVAL, "NULL argument");
     if (flags & ~PA_UNCONSTRAINED) return fail(PA_EINVAL, "unknown flags 0x%x", flags);
-    if (op->mat != PA_MAT_ELEM_ISO) return fail(PA_EUNSUPPORTED, "diagonal of general material data is not built");
-    if (op->geo != PA_GEOM_AFFINE) return fail(PA_EUNSUPPORTED, "diagonal of non-affine geometry is not built");
     return launch_diagonal(op, d, (flags & PA_UNCONSTRAINED) ? 0 : 1);
 }
 

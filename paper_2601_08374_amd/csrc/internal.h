@@ -153,6 +153,8 @@ struct pa_op {
     pa::AblationBuffers* abl = nullptr;   // pa_elast_apply_variant work arrays
     int mat = PA_MAT_ELEM_ISO;       // material data form
     void* md = nullptr;              // device material data of dtype (PA_MAT_QP_ISO, PA_MAT_ANISO)
+    bool md_point_major = false;     // md word k of point alpha of element e at (2 alpha + k) NE + e
+    std::vector<double> mdata;       // host copy of per-point Lame data [NE][q^3][2] (solver hierarchies)
     int geo = PA_GEOM_AFFINE;        // element geometry form
     void* gd = nullptr;              // device geometry data of dtype (PA_GEOM_QP_DATA, PA_GEOM_TRILINEAR)
     // unstructured mesh (pa_elast_setup_unstructured); kmap == nullptr on the box

@@ -45,6 +45,10 @@ __device__ __forceinline__ NodeCands node_candidates(const Geom& g, int p, int g
 // setup.hip
 int tables_words(int p, int q);
 int compute_tables(int p, int q, hipStream_t s, double** d_tab, Tables* host);
+// Operator with general material data on the box (kind PA_MAT_QP_ISO or PA_MAT_ANISO,
+// data validated by the caller).
+int create_material_op(const MeshDesc& md, int p, int q, int kind, const double* data, int dtype, hipStream_t s,
+                       pa_op** out);
 int compute_element_data(const MeshDesc& m, const double* d_vert, const double* d_lam, const double* d_mu,
                          int dtype, void* ed, hipStream_t s);
 int launch_diagonal(const pa_op* op, void* d, int constrained);

@@ -252,10 +252,80 @@ __global__ void diagonal_kernel(T* __restrict__ dg, const T* __restrict__ ed, co
     for (int c = 0; c < 3; ++c) dg[(size_t)c * g.Nn + node] = (T)acc[c];
 }
 
+// Per-point Lame parameters: the quadrature sum of the diagonal entry written out,
+//   diag(c, a) += sum_alpha w_alpha detJ [lambda_alpha g_c^2 + mu_alpha (|g|^2 + g_c^2)],
+//   g = J^{-T} grad_ref phi_a(alpha), grad_ref phi_a = (G_x B_y B_z, B_x G_y B_z, B_x B_y G_z),
+// with md word k of point alpha of element e at md_word(e, alpha, k) (element-major
+// [NE][q^3][2], or point-major [2 q^3][NE] for the linear-element kernel's layout).
+template <typename T>
+__device__ __forceinline__ void diagonal_part_qp(const T* __restrict__ ed, const T* __restrict__ md, bool pm,
+                                                 int NE, const double* __restrict__ tab, int D, int q, int e, int ix,
+                                                 int iy, int iz, double (&out)[3]) {
+    const double* w = tab + D + q;
+    const double* B = w + q;
+    const double* G = B + D * q;
+    const T* o = ed + (size_t)e * kEdStride;
+    double Ji[9];
+    for (int k = 0; k < 9; ++k) Ji[k] = (double)o[k];
+    const double detJ = (double)o[9];   // unit Lame parameters in the element data
+    const int Q3 = q * q * q;
+    out[0] = out[1] = out[2] = 0.0;
+    for (int qz = 0; qz < q; ++qz) {
+        const double bz = B[iz * q + qz], gz = G[iz * q + qz];
+        for (int qy = 0; qy < q; ++qy) {
+            const double by = B[iy * q + qy], gy = G[iy * q + qy];
+            for (int qx = 0; qx < q; ++qx) {
+                const double bx = B[ix * q + qx], gx = G[ix * q + qx];
+                const double r[3] = {gx * by * bz, bx * gy * bz, bx * by * gz};
+                double gr[3];
+                for (int c = 0; c < 3; ++c) gr[c] = Ji[c] * r[0] + Ji[3 + c] * r[1] + Ji[6 + c] * r[2];
+                const int al = qx + q * (qy + q * qz);
+                const size_t i0 = pm ? (size_t)(2 * al) * NE + e : ((size_t)e * Q3 + al) * 2;
+                const size_t i1 = pm ? i0 + (size_t)NE : i0 + 1;
+                const double W = w[qx] * w[qy] * w[qz] * detJ;
+                const double lam = (double)md[i0], mu = (double)md[i1];
+                const double n2 = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
+                for (int c = 0; c < 3; ++c) out[c] += W * (lam * gr[c] * gr[c] + mu * (n2 + gr[c] * gr[c]));
+            }
+        }
+    }
+}
+
+template <typename T>
+__global__ void diagonal_qp_kernel(T* __restrict__ dg, const T* __restrict__ ed, const T* __restrict__ md, int pm,
+                                   const double* __restrict__ tab, int p, int q, Geom g) {
+    const int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= g.Nn) return;
+    const int gx = node % g.Nx, gy = (node / g.Nx) % g.Ny, gz = node / (g.Nx * g.Ny);
+    const NodeCands nc = node_candidates(g, p, gx, gy, gz);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int kz = 0; kz < 2; ++kz)
+        for (int ky = 0; ky < 2; ++ky)
+            for (int kx = 0; kx < 2; ++kx) {
+                if (!(nc.v[0][kx] && nc.v[1][ky] && nc.v[2][kz])) continue;
+                const int e = nc.e[0][kx] + g.nx * (nc.e[1][ky] + g.ny * nc.e[2][kz]);
+                double part[3];
+                diagonal_part_qp(ed, md, pm != 0, g.NE, tab, p + 1, q, e, nc.l[0][kx], nc.l[1][ky], nc.l[2][kz],
+                                 part);
+                for (int c = 0; c < 3; ++c) acc[c] += part[c];
+            }
+    for (int c = 0; c < 3; ++c) dg[(size_t)c * g.Nn + node] = (T)acc[c];
+}
+
 int launch_diagonal(const pa_op* op, void* d, int constrained) {
+    if (op->mat == PA_MAT_ANISO) return fail(PA_EUNSUPPORTED, "diagonal of anisotropic material data is not built");
+    if (op->geo != PA_GEOM_AFFINE) return fail(PA_EUNSUPPORTED, "diagonal of non-affine geometry is not built");
     const Geom g = make_geom(op->mesh, op->p, constrained != 0);
     const int nb = (g.Nn + 255) / 256;
-    if (op->dtype == PA_F64)
+    if (op->mat == PA_MAT_QP_ISO) {
+        const int pm = op->md_point_major ? 1 : 0;
+        if (op->dtype == PA_F64)
+            hipLaunchKernelGGL(diagonal_qp_kernel<double>, dim3(nb), dim3(256), 0, op->stream, (double*)d,
+                               (const double*)op->ed, (const double*)op->md, pm, op->d_tab, op->p, op->q, g);
+        else
+            hipLaunchKernelGGL(diagonal_qp_kernel<float>, dim3(nb), dim3(256), 0, op->stream, (float*)d,
+                               (const float*)op->ed, (const float*)op->md, pm, op->d_tab, op->p, op->q, g);
+    } else if (op->dtype == PA_F64)
         hipLaunchKernelGGL(diagonal_kernel<double>, dim3(nb), dim3(256), 0, op->stream, (double*)d,
                            (const double*)op->ed, op->d_tab, op->p, op->q, g);
     else

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import synthetic as syn
-from oracle import material, mesh as omesh
+from oracle import elasticity, material, mesh as omesh, solvers
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -207,6 +207,12 @@ def test_material_errors():
         with pytest.raises(pa.PaError) as ei:
             call()
         assert ei.value.code == pa.capi.PA_EUNSUPPORTED
+    # per-point Lame data: the hierarchy needs a coarser level than the finest
+    qpop = pa.Operator.with_material(syn.BoxMesh(n=(3, 2, 2), clamped_faces=1), 1, pa.PA_MAT_QP_ISO,
+                                     np.ones((12, 27, 2)))
+    with pytest.raises(pa.PaError) as ei:
+        qpop.hierarchy()
+    assert ei.value.code == pa.capi.PA_EUNSUPPORTED
     with pytest.raises(pa.PaError) as ei:   # a mesh without elements is rejected like pa_elast_setup's
         pa.Operator.with_material(syn.BoxMesh(n=(0, 2, 2)), 2, pa.PA_MAT_ANISO, np.zeros((0, 21)))
     assert ei.value.code == pa.capi.PA_EINVAL
@@ -223,3 +229,75 @@ def test_material_single_element(p, kind):
     x = syn.uniform_vector(op.N, seed=4)
     ref = material.GeneralOperator(mesh, p, p + 2, C).apply(x, constrained=True)
     assert _rel(_gpu(op, x, 0), ref) <= TOL[0]
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 8])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_qp_diagonal_parity(p, dtype):
+    """Diagonal with per-point Lame data (the Jacobi smoother's diagonal) vs the oracle's
+    element matrices; both layouts of the data (point-major at p = 1)."""
+    pa = _pa()
+    print(f"per-point diagonal p={p} dtype={dtype}", flush=True)
+    mesh = _mesh(p, seed=60 + p) if p < 8 else syn.BoxMesh(n=(2, 1, 1), L=(1.0, 0.6, 0.7), A=syn.SHEAR_A,
+                                                            clamped_faces=0b000001)
+    NE, q = mesh.num_elements, p + 2
+    data, C = _material(pa.PA_MAT_QP_ISO, NE, q, seed=p)
+    op = pa.Operator.with_material(mesh, p, pa.PA_MAT_QP_ISO, data, dtype=dtype)
+    ref = material.GeneralOperator(mesh, p, q, C)
+    for flags, constrained in ((0, True), (pa.PA_UNCONSTRAINED, False)):
+        d = op.diagonal(flags)
+        torch.cuda.synchronize()
+        want = ref.diagonal(constrained)
+        assert _rel(d.double().cpu().numpy(), want) <= TOL[dtype], flags
+
+
+def _qp_problem(p, seed):
+    """A clamped box whose hierarchy has a coarser level, with per-point Lame data that
+    varies by +-40% inside every element around its element material (two materials,
+    E = 1 and 100, below p = 4)."""
+    mesh = {1: syn.BoxMesh(n=(4, 4, 4), L=(2.0, 1.0, 1.0), A=syn.SHEAR_A, clamped_faces=1),
+            2: syn.graded_mesh((4, 2, 2), seed=seed, L=(2.0, 1.0, 1.0), clamped_faces=1),
+            4: syn.graded_mesh((3, 2, 2), seed=seed, L=(1.5, 1.0, 1.0), clamped_faces=1)}[p]
+    NE, q = mesh.num_elements, p + 2
+    if p < 4:
+        lam_e, mu_e = syn.two_material_lame(NE, seed=seed)
+    else:   # one base material: a residual of 1e-10 stays within FP64 reach at p = 4
+        lam_e, mu_e = (np.full(NE, v) for v in syn.lame_from_young_poisson(1.0, 0.3))
+    lam, mu = syn.quadrature_point_lame(lam_e, mu_e, q, seed=seed + 1, spread=0.4)
+    ref = material.GeneralOperator(mesh, p, q, material.isotropic_voigt(lam, mu))
+    b = elasticity.body_force_vector(mesh, p, q, (0.1, -0.2, -1.0))
+    b[ref.ess] = 0.0
+    return mesh, np.stack([lam, mu], axis=-1), ref, b
+
+
+@pytest.mark.parametrize("p", [1, 2, 4])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_qp_material_solve_vs_direct(p, mode):
+    """GMG-PCG with per-point Lame data on the finest level (coarser levels take the
+    quadrature-weighted element means): the solution of the constrained system vs a dense
+    direct solve of the oracle's assembled matrix, in all three solver modes."""
+    pa = _pa()
+    print(f"per-point material solve p={p} mode={mode}", flush=True)
+    mesh, data, ref, b = _qp_problem(p, seed=30 + p)
+    u = solvers.solve_dense(ref.dense(True), b)
+    op = pa.Operator.with_material(mesh, p, pa.PA_MAT_QP_ISO, data)
+    x, info, rc = op.solve(torch.tensor(b, device="cuda"), rtol=1e-10, mode=mode, stop=1, cheb_degree=3,
+                           h_levels=1 if p == 1 else 0)
+    assert rc == 0, (rc, info.iters)
+    assert info.rel_res_true <= 1e-10 * (1 + 1e-6)
+    got = x.cpu().numpy()
+    assert _rel(got, u) <= 1e-7, _rel(got, u)
+    print(f"  iters {info.iters} outer {info.outer_iters} err {_rel(got, u):.2e}")
+
+
+def test_qp_material_solve_fp32_operator():
+    """An FP32 operator with per-point data: the FP64 outer operator is rebuilt from the
+    host copy of the data, so the FP64 solve meets the same tolerance."""
+    pa = _pa()
+    mesh, data, ref, b = _qp_problem(2, seed=41)
+    u = solvers.solve_dense(ref.dense(True), b)
+    op = pa.Operator.with_material(mesh, 2, pa.PA_MAT_QP_ISO, data, dtype=pa.PA_F32)
+    for mode in (0, 1):
+        x, info, rc = op.solve(torch.tensor(b, device="cuda"), rtol=1e-10, mode=mode, stop=1, cheb_degree=3)
+        assert rc == 0 and info.rel_res_true <= 1e-10 * (1 + 1e-6)
+        assert _rel(x.cpu().numpy(), u) <= 1e-7
