@@ -4,7 +4,8 @@ Solver: the 8:1:1 cantilever (80x8x8 hexahedra, clamped at x=0, unit downward
 traction on x=8, E=1, nu=0.3) at p in {4,6,8}: plain FP64 GMG-PCG, the FP32 apply /
 FP32 V-cycle inside FP64 iterative refinement, and FP64 PCG preconditioned by the
 FP32 V-cycle, all to a true relative residual of 1e-8, with p-hierarchy down to 1
-and 2 h-levels, Chebyshev(3)-Jacobi smoothing.
+and 2 h-levels, Chebyshev(3)-Jacobi smoothing; at p = 8 also with the material
+given per quadrature point.
 
 Apply: the cumulative ablation (unfused variants vs the fused kernel), the fused
 apply with the three material data forms, the fused apply on trilinear
@@ -17,9 +18,12 @@ import time
 import numpy as np
 
 
-def _solve(pa, torch, mesh, p, lam, mu, mode, reps=3):
+def _solve(pa, torch, mesh, p, lam, mu, mode, reps=3, qp_data=None):
     NE = mesh.num_elements
-    op = pa.Operator(mesh, p, np.full(NE, lam), np.full(NE, mu))
+    if qp_data is None:
+        op = pa.Operator(mesh, p, np.full(NE, lam), np.full(NE, mu))
+    else:
+        op = pa.Operator.with_material(mesh, p, pa.PA_MAT_QP_ISO, qp_data)
     b = op.rhs((0.0, 0.0, 0.0), 1, (0.0, 0.0, -1.0))
     best = None
     for _ in range(reps):
@@ -65,6 +69,21 @@ def cantilever_solves(torch, dev, ps=(4, 6, 8)):
             del x32, e, Ae
         del x64, Ax, op
         torch.cuda.empty_cache()
+    # the same cantilever with the material at every quadrature point (the paper's PA data
+    # form): the finest level keeps the per-point data, coarser levels its element means
+    pq = ps[-1]
+    NE = mesh.num_elements
+    lq, mq = syn.quadrature_point_lame(np.full(NE, lam), np.full(NE, mu), pq + 2, seed=11, spread=0.4)
+    data = np.stack([lq, mq], axis=-1)
+    qrec = {"workload": f"p={pq}, per-point lambda, mu = the E=1, nu=0.3 values x (1 + 0.4 u), u ~ U[-1,1] "
+                        "independently per point (seed 11); otherwise as above"}
+    for mode, name in ((pa.PA_SOLVE_F64, "f64"), (pa.PA_SOLVE_F32_PREC, "f32_prec")):
+        r, x, op = _solve(pa, torch, mesh, pq, lam, mu, mode, qp_data=data)
+        r["time_vs_element_data"] = r["solve_s"] / out[f"p{pq}"][name]["solve_s"]
+        qrec[name] = r
+        del x, op
+        torch.cuda.empty_cache()
+    out[f"p{pq}_qpoint"] = qrec
     return out
 
 
