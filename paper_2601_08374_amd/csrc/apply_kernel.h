@@ -754,17 +754,68 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
     }
 }
 
+// The element-boundary nodes of the box numbered compactly, so that the skeleton kernel's
+// lanes all have work: z-layers in order; a layer on element faces (gz % p == 0) holds
+// all Nx Ny nodes; any other layer holds, per element slab of rows, the full row
+// gy % p == 0 and the nodes gx % p == 0 of the p - 1 rows after it, then the last full row.
+struct SkelNodes {
+    int full;    // nodes of a face layer: Nx Ny
+    int row;     // nodes of one element slab of rows in an inner layer: Nx + (p - 1)(nx + 1)
+    int inner;   // nodes of an inner layer: ny row + Nx
+    int slab;    // nodes of one element slab of layers: full + (p - 1) inner
+    int total;   // nz slab + full
+};
+
+inline SkelNodes skel_nodes(const Geom& g, int p) {
+    SkelNodes s;
+    s.full = g.Nx * g.Ny;
+    s.row = g.Nx + (p - 1) * (g.nx + 1);
+    s.inner = g.ny * s.row + g.Nx;
+    s.slab = s.full + (p - 1) * s.inner;
+    s.total = g.nz * s.slab + s.full;
+    return s;
+}
+
+template <int P>
+__host__ __device__ __forceinline__ void skel_node_coords(int t, const SkelNodes& s, const Geom& g, int& gx,
+                                                           int& gy, int& gz) {
+    const int ez = t / s.slab;
+    int r = t - ez * s.slab;
+    if (r < s.full) {
+        gz = ez * P;
+        gy = r / g.Nx;
+        gx = r - gy * g.Nx;
+        return;
+    }
+    r -= s.full;
+    const int j = r / s.inner;
+    r -= j * s.inner;
+    gz = ez * P + 1 + j;
+    const int ey = r / s.row;
+    r -= ey * s.row;
+    if (r < g.Nx) {
+        gy = ey * P;
+        gx = r;
+        return;
+    }
+    r -= g.Nx;
+    const int k = r / (g.nx + 1);
+    gy = ey * P + 1 + k;
+    gx = (r - k * (g.nx + 1)) * P;
+}
+
 // Kernel 2: for every element-boundary node, sum the skeleton contributions of its
 // elements in a fixed order and write y.
 template <int P, typename T>
 __global__ void __launch_bounds__(256)
-pa_skeleton_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ sk, const Geom g, const int add) {
+pa_skeleton_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ sk, const Geom g,
+                   const SkelNodes sn, const int add) {
     using SK = Skel<P + 1>;
-    const int node = blockIdx.x * blockDim.x + threadIdx.x;
-    if (node >= g.Nn) return;
-    const int gx = node % g.Nx, r = node / g.Nx;
-    const int gy = r % g.Ny, gz = r / g.Ny;
-    if (gx % P != 0 && gy % P != 0 && gz % P != 0) return;   // interior node: written by its element
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= sn.total) return;
+    int gx, gy, gz;
+    skel_node_coords<P>(t, sn, g, gx, gy, gz);
+    const int node = gx + g.Nx * (gy + g.Ny * gz);
     const NodeCands nc = node_candidates(g, P, gx, gy, gz);
     const size_t NN = (size_t)g.Nn;
     const bool cl = g.clamp && clamped_node(g.clamp, gx, gy, gz, g);
@@ -845,9 +896,10 @@ int launch_apply_typed(const ApplyLaunch& L) {
         }
         return PA_OK;
     }
-    const int nb2 = (L.g.Nn + 255) / 256;
+    const SkelNodes sn = skel_nodes(L.g, P);
+    const int nb2 = (sn.total + 255) / 256;
     hipLaunchKernelGGL((pa_skeleton_kernel<P, T>), dim3(nb2), dim3(256), 0, L.stream, (const T*)L.x, (T*)L.y,
-                       (const T*)L.sk, L.g, L.add);
+                       (const T*)L.sk, L.g, sn, L.add);
     PA_HIP(hipGetLastError());
     return PA_OK;
 }
