@@ -385,6 +385,12 @@ enum : int { kMatElemIso = 0, kMatQpIso = 1, kMatAniso = 2 };
 // The non-affine forms take ed[9], ed[10] = lambda, mu (no det J).
 enum : int { kGeoAffine = 0, kGeoQp = 1, kGeoTri = 2 };
 
+// Unstructured kernels that keep the block's element-to-node map in LDS instead of each
+// line's node ids in registers: where that raises the number of waves per SIMD (FP64 at
+// p = 1 and p = 8; elsewhere the LDS copy measured slower).
+template <int P, typename T>
+constexpr bool kUnsIdsInLds = sizeof(T) == 8 && (P == 1 || P == 8);
+
 // UNS: unstructured mesh.  Nodes come from the element-to-node map kmap (global node,
 // kClampBit on clamped nodes; g.clamp != 0 for a constrained apply), element-interior
 // nodes go to y directly and element-boundary nodes to the skeleton entry kpos of
@@ -408,6 +414,9 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
     __shared__ T Cs[MAT == kMatAniso || GEO == kGeoTri ? E * 21 : 1];   // stiffness or trilinear coefficients
     __shared__ int ebase[E];          // first node of each element, or -1 past the end
     __shared__ int ecoord[E][3];
+    // unstructured: node ids of the element lines in registers, or (KL) the block's map in LDS
+    constexpr bool KL = UNS && kUnsIdsInLds<P, T>;
+    __shared__ int Ks[KL ? E * D * D * D : 1];
 
     const int tid = threadIdx.x;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -427,6 +436,10 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
         } else {
             ebase[tid] = -1;
         }
+    }
+    if constexpr (KL) {
+        for (int w = tid; w < E * D * D * D; w += NT)
+            Ks[w] = w < ne_blk * (D * D * D) ? kmap[(size_t)e0 * (D * D * D) + w] : 0;
     }
     for (int w = tid; w < E * kEdStride; w += NT)
         Es[w] = w < ne_blk * kEdStride ? ed[(size_t)e0 * kEdStride + w] : T(0);
@@ -450,12 +463,17 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
     constexpr int NL = E * D * D;
     constexpr int GX = (NL + NT - 1) / NT;
     static_assert(GX * D <= 32, "clamp mask bits");
-    int ln_node[GX];       // global node of (ix = 0) of the line, or -1
+    int ln_node[GX];       // global node of (ix = 0) of the line (unstructured: 0, KL: its word in Ks), or -1
     int ln_slot[GX];       // skeleton slot of (ix = 0) of the line
     unsigned ln_full = 0u; // bit j: the line lies on the element boundary
     unsigned ln_cl = 0u;   // bit j*D + ix: clamped node (read as 0)
-    int ln_nodes[UNS ? GX : 1][UNS ? D : 1];   // unstructured: every node of the line
-    __syncthreads();       // ebase, ecoord, Es ready
+    int ln_nodes[UNS && !KL ? GX : 1][UNS && !KL ? D : 1];   // unstructured: every node of the line
+    // global node of node ix of line j (the map word without its clamp flag)
+    auto uns_node = [&](int j, int ix) -> size_t {
+        if constexpr (KL) return (unsigned)Ks[ln_node[j] + ix] & ~kClampBit;
+        else return (size_t)ln_nodes[UNS ? j : 0][UNS ? ix : 0];
+    };
+    __syncthreads();       // ebase, ecoord, Es, Ks ready
 #pragma unroll
     for (int j = 0; j < GX; ++j) {
         ln_node[j] = -1;
@@ -467,13 +485,20 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
             const int b = ebase[el];
             ln_slot[j] = SK::index(0, iy, iz);
             if (SK::full_row(iy, iz)) ln_full |= 1u << j;
-            if (UNS && b >= 0) {
+            if (KL && b >= 0) {
+                ln_node[j] = el * (D * D * D) + D * (iy + D * iz);
+                if (g.clamp) {
+#pragma unroll
+                    for (int ix = 0; ix < D; ++ix)
+                        if ((unsigned)Ks[ln_node[j] + ix] & kClampBit) ln_cl |= 1u << (j * D + ix);
+                }
+            } else if (UNS && b >= 0) {
                 ln_node[j] = 0;
                 const int* mp = kmap + (size_t)(e0 + el) * (D * D * D) + D * (iy + D * iz);
 #pragma unroll
                 for (int ix = 0; ix < D; ++ix) {
                     const unsigned v = (unsigned)mp[ix];
-                    ln_nodes[UNS ? j : 0][UNS ? ix : 0] = (int)(v & ~kClampBit);
+                    ln_nodes[UNS && !KL ? j : 0][UNS && !KL ? ix : 0] = (int)(v & ~kClampBit);
                     if (g.clamp && (v & kClampBit)) ln_cl |= 1u << (j * D + ix);
                 }
             } else if (b >= 0) {
@@ -494,7 +519,7 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
 #pragma unroll
             for (int ix = 0; ix < D; ++ix)
                 xr[j][ix] = (ln_node[j] >= 0 && !((ln_cl >> (j * D + ix)) & 1u))
-                                ? x[c * NN + (UNS ? (size_t)ln_nodes[UNS ? j : 0][UNS ? ix : 0] : ln_node[j] + ix)]
+                                ? x[c * NN + (UNS ? uns_node(j, ix) : (size_t)(ln_node[j] + ix))]
                                 : T(0);
     };
     line_load(0);
@@ -734,7 +759,7 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
                     if constexpr (UNS) {
                         if (inner) {
                             // sole owner; a clamped interior node keeps its input in a constrained apply
-                            const size_t o = c * NN + ln_nodes[j][ix];
+                            const size_t o = c * NN + uns_node(j, ix);
                             const T v = ((ln_cl >> (j * D + ix)) & 1u) ? x[o] : yo[ix];
                             y[o] = add ? y[o] + v : v;
                         } else {
