@@ -18,7 +18,7 @@
 // contributions of its (up to 8) elements in a fixed order and writes y -- no
 // atomics, no separate initialisation of y, bitwise-reproducible results.
 //
-// From p = 4 on every 1D contraction uses the even-odd decomposition: on the
+// From p = 3 on every 1D contraction uses the even-odd decomposition: on the
 // symmetric Gauss-Lobatto / Gauss-Legendre point sets B[i][k] = B[D-1-i][Q-1-k]
 // and G[i][k] = -G[D-1-i][Q-1-k], so pairs of outputs k, Q-1-k come from the
 // sums and differences of mirrored inputs with half-size tables.
@@ -182,9 +182,10 @@ __device__ __forceinline__ void eo_contract(const T (&in)[NI], T (&out)[NO], con
     }
 }
 
-// Even-odd tables from p = 4 on (D >= 5); plain tables below.
+// Even-odd tables from p = 3 on (D >= 4: fewer instructions and no scalar-register spills
+// of the tables there); plain tables below, where the even-odd form saves no instruction.
 template <int NI, int NO>
-constexpr bool kEvenOdd = NI >= 5 && NO >= 5;
+constexpr bool kEvenOdd = NI >= 4 && NO >= 4;
 
 template <typename T, int NI, int NO, bool EO = kEvenOdd<NI, NO>>
 struct TabSel {
