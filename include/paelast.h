@@ -152,13 +152,15 @@ int pa_elast_setup(const pa_mesh_t* m, int p, int q, const double* lambda, const
  * eps_V = (e_xx, e_yy, e_zz, 2 e_yz, 2 e_xz, 2 e_xy).  The data is copied.  q must be
  * p + 2 (PA_EUNSUPPORTED otherwise); other arguments and errors as pa_elast_setup
  * (PA_EINVAL for a point or element that violates the conditions above).  apply and
- * rhs work as for pa_elast_setup operators.  PA_MAT_QP_ISO operators also take
- * pa_elast_diagonal, gmg_setup and gmg_pcg_solve: the finest level keeps the
- * per-point data (the library keeps a host copy of it to build that level in the
- * solver's precision), coarser levels take the quadrature-weighted element means of
- * lambda and mu; a hierarchy with no level below the finest returns
- * PA_EUNSUPPORTED (its coarse matrix is assembled from per-element parameters).
- * PA_MAT_ANISO operators return PA_EUNSUPPORTED from all three. */
+ * rhs work as for pa_elast_setup operators, and so do pa_elast_diagonal, gmg_setup
+ * and gmg_pcg_solve: the finest level keeps the material data (the library keeps a
+ * host copy of it to build that level in the solver's precision); coarser levels
+ * take per-element isotropic parameters, the quadrature-weighted element means of
+ * per-point lambda and mu, or for an anisotropic C the isotropic stiffness with the
+ * same traces of its normal and shear blocks (mu = (C44 + C55 + C66) / 3, 9 lambda +
+ * 6 mu = the sum of the normal block).  A hierarchy with no level below the finest
+ * returns PA_EUNSUPPORTED (its coarse matrix is assembled from per-element
+ * parameters). */
 int pa_elast_setup_material(const pa_mesh_t* m, int p, int q, int kind, const double* data, int dtype,
                             void* hip_stream, pa_op_t** out);
 /* The operator on non-affine (trilinear) hexahedra.  The paper's kernels take affine
@@ -236,10 +238,11 @@ int pa_elast_apply_ex(pa_op_t* op, const void* x, void* y, int flags);
 int pa_elast_apply_variant(pa_op_t* op, const void* x, void* y, int flags, int variant);
 /* d = diag(A) (async), the Jacobi diagonal of Sec. 3.1, from 1D-factorized
  * integrals of products of reference derivatives (per-point Lame data: the
- * quadrature sum over the element's points).  Constrained unless flags has
- * PA_UNCONSTRAINED (then clamped entries hold the true diagonal; otherwise 1).
- * d: device array of N elements of the op's dtype.  PA_EUNSUPPORTED for
- * anisotropic material data and non-affine or unstructured operators. */
+ * quadrature sum over the element's points; anisotropic C: the same 1D-factorized
+ * integrals contracted with C).  Constrained unless flags has PA_UNCONSTRAINED (then
+ * clamped entries hold the true diagonal; otherwise 1).  d: device array of N
+ * elements of the op's dtype.  PA_EUNSUPPORTED for non-affine or unstructured
+ * operators. */
 int pa_elast_diagonal(pa_op_t* op, void* d, int flags);
 
 /* b = load vector of eq. 4 (async): integral of f.v over the box plus integral

@@ -217,10 +217,23 @@ int create_material_op(const MeshDesc& md, int p, int q, int kind, const double*
     if (rc) return rc;
     op->mat = kind;
     op->md_point_major = lin;
+    // kept for solver hierarchies: the data itself (level operators in another precision)
+    // and per-element isotropic parameters for the coarse levels
+    op->mdata.assign(data, data + NE * per);
+    if (kind == PA_MAT_ANISO) {
+        // the isotropic stiffness with the same traces of the normal block (9 lambda + 6 mu)
+        // and of the shear block (3 mu): positive for a positive definite C
+        for (int64_t e = 0; e < NE; ++e) {
+            // upper triangle row by row: (0,0) 0, (0,1) 1, (0,2) 2, (1,1) 6, (1,2) 7, (2,2) 11,
+            // (3,3) 15, (4,4) 18, (5,5) 20
+            const double* c = data + e * 21;
+            const double m = (c[15] + c[18] + c[20]) / 3.0;
+            const double n = c[0] + c[6] + c[11] + 2.0 * (c[1] + c[2] + c[7]);
+            op->lam[e] = (n - 6.0 * m) / 9.0;
+            op->mu[e] = m;
+        }
+    }
     if (kind == PA_MAT_QP_ISO) {
-        // kept for solver hierarchies: the data itself (level operators in another precision)
-        // and its quadrature-weighted element means (the coarse levels' per-element parameters)
-        op->mdata.assign(data, data + NE * per);
         for (int64_t e = 0; e < NE; ++e) {
             double sl = 0.0, sm = 0.0, sw = 0.0;
             for (int kz = 0; kz < q; ++kz)

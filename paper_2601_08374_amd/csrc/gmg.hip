@@ -370,10 +370,10 @@ void destroy_gmg(pa_gmg* G) {
 }
 
 int setup_gmg(pa_op* op, const pa_solve_opts_t* o, pa_gmg** out) {
-    if (op->mat != PA_MAT_ELEM_ISO && op->mat != PA_MAT_QP_ISO)
-        return fail(PA_EUNSUPPORTED, "the multigrid hierarchy needs isotropic Lame parameters");
     if (op->geo != PA_GEOM_AFFINE || op->kmap) return fail(PA_EUNSUPPORTED, "the multigrid hierarchy needs the affine box");
-    const bool qp = op->mat == PA_MAT_QP_ISO;
+    // general material data: the finest level keeps it, coarser levels take per-element
+    // isotropic parameters derived from it (op->lam, op->mu)
+    const bool gen = op->mat != PA_MAT_ELEM_ISO;
     pa_solve_opts_t opts;
     if (o) opts = *o; else pa_solve_opts_default(&opts);
     if (opts.mode != PA_SOLVE_F64 && opts.mode != PA_SOLVE_F32_IR && opts.mode != PA_SOLVE_F32_PREC)
@@ -401,15 +401,16 @@ int setup_gmg(pa_op* op, const pa_solve_opts_t* o, pa_gmg** out) {
                       (long long)Nc);
             break;
         }
-        if (qp && plan.size() < 2) {
+        if (gen && plan.size() < 2) {
             // the coarse matrix is assembled from per-element Lame parameters
-            rc = fail(PA_EUNSUPPORTED, "per-point Lame data needs at least one coarser level (p > 1 or h-levels)");
+            rc = fail(PA_EUNSUPPORTED, "general material data needs at least one coarser level (p > 1 or h-levels)");
             break;
         }
         G->L.resize(plan.size());
         // level operators: per-element Lame parameters follow the element map of the coarsening;
-        // with per-point data the finest level keeps it, and the coarser levels take its
-        // quadrature-weighted element means (op->lam, op->mu)
+        // with general material data the finest level keeps it, and the coarser levels take
+        // op->lam, op->mu (quadrature-weighted element means of per-point data; the
+        // trace-matched isotropic stiffness of an anisotropic C)
         std::vector<double> lam = op->lam, mu = op->mu;
         for (size_t l = 0; l < plan.size() && !rc; ++l) {
             Level& v = G->L[l];
@@ -438,9 +439,8 @@ int setup_gmg(pa_op* op, const pa_solve_opts_t* o, pa_gmg** out) {
                 lam.swap(cl);
                 mu.swap(cm);
             }
-            if (l == 0 && qp)
-                rc = create_material_op(P.mesh, P.p, op->q, PA_MAT_QP_ISO, op->mdata.data(), G->vdtype, G->stream,
-                                        &v.op);
+            if (l == 0 && gen)
+                rc = create_material_op(P.mesh, P.p, op->q, op->mat, op->mdata.data(), G->vdtype, G->stream, &v.op);
             else
                 rc = create_op(P.mesh, P.p, P.p + (op->q - op->p), lam.data(), mu.data(), G->vdtype, G->stream,
                                &v.op);
@@ -528,7 +528,7 @@ int setup_gmg(pa_op* op, const pa_solve_opts_t* o, pa_gmg** out) {
         if (op->dtype == PA_F64) {
             G->fine64 = op;
         } else {
-            rc = qp ? create_material_op(op->mesh, op->p, op->q, PA_MAT_QP_ISO, op->mdata.data(), PA_F64, G->stream,
+            rc = gen ? create_material_op(op->mesh, op->p, op->q, op->mat, op->mdata.data(), PA_F64, G->stream,
                                          &G->fine64)
                     : create_op(op->mesh, op->p, op->q, op->lam.data(), op->mu.data(), PA_F64, G->stream, &G->fine64);
             if (rc) break;

@@ -291,6 +291,75 @@ __device__ __forceinline__ void diagonal_part_qp(const T* __restrict__ ed, const
     }
 }
 
+// Per-element anisotropic Voigt stiffness C (md = [NE][21], upper triangle row by row):
+// a unit displacement in direction c at node a has the engineering strain S_c g with
+// g = grad phi_a, so diag(c, a) = sum_ij C[v_c(i)][v_c(j)] int d_i phi_a d_j phi_a, where
+// v_c(i) is the Voigt row of strain component d_i u_c: v_0 = (0, 5, 4), v_1 = (5, 1, 3),
+// v_2 = (4, 3, 2); the integrals come from the 1D-factorized M as in diagonal_part.
+template <typename T>
+__device__ __forceinline__ void diagonal_part_aniso(const T* __restrict__ ed, const T* __restrict__ md,
+                                                    const double* __restrict__ tab, int D, int q, int e, int ix,
+                                                    int iy, int iz, double (&out)[3]) {
+    const double* bb = tab + D + 2 * q + 2 * D * q;
+    const double* bg = bb + D;
+    const double* gg = bg + D;
+    const int idx[3] = {ix, iy, iz};
+    double M[3][3];
+    for (int m = 0; m < 3; ++m)
+        for (int n = 0; n < 3; ++n) {
+            double f = 1.0;
+            for (int d = 0; d < 3; ++d) {
+                const int i = idx[d];
+                f *= (m == d && n == d) ? gg[i] : ((m == d || n == d) ? bg[i] : bb[i]);
+            }
+            M[m][n] = f;
+        }
+    const T* o = ed + (size_t)e * kEdStride;
+    double Ji[9];
+    for (int k = 0; k < 9; ++k) Ji[k] = (double)o[k];
+    double P[3][3];   // int d_i phi_a d_j phi_a / det J
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int m = 0; m < 3; ++m)
+                for (int n = 0; n < 3; ++n) s += Ji[m * 3 + i] * M[m][n] * Ji[n * 3 + j];
+            P[i][j] = s;
+        }
+    const T* c = md + (size_t)e * 21;
+    auto C = [&](int a, int b) -> double {
+        const int lo = a < b ? a : b, hi = a < b ? b : a;
+        return (double)c[lo * 6 - lo * (lo - 1) / 2 + (hi - lo)];
+    };
+    constexpr int v[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
+    const double detJ = (double)o[9];   // unit Lame parameters in the element data
+    for (int k = 0; k < 3; ++k) {
+        double s = 0.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) s += C(v[k][i], v[k][j]) * P[i][j];
+        out[k] = detJ * s;
+    }
+}
+
+template <typename T>
+__global__ void diagonal_aniso_kernel(T* __restrict__ dg, const T* __restrict__ ed, const T* __restrict__ md,
+                                      const double* __restrict__ tab, int p, int q, Geom g) {
+    const int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= g.Nn) return;
+    const int gx = node % g.Nx, gy = (node / g.Nx) % g.Ny, gz = node / (g.Nx * g.Ny);
+    const NodeCands nc = node_candidates(g, p, gx, gy, gz);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int kz = 0; kz < 2; ++kz)
+        for (int ky = 0; ky < 2; ++ky)
+            for (int kx = 0; kx < 2; ++kx) {
+                if (!(nc.v[0][kx] && nc.v[1][ky] && nc.v[2][kz])) continue;
+                const int e = nc.e[0][kx] + g.nx * (nc.e[1][ky] + g.ny * nc.e[2][kz]);
+                double part[3];
+                diagonal_part_aniso(ed, md, tab, p + 1, q, e, nc.l[0][kx], nc.l[1][ky], nc.l[2][kz], part);
+                for (int c = 0; c < 3; ++c) acc[c] += part[c];
+            }
+    for (int c = 0; c < 3; ++c) dg[(size_t)c * g.Nn + node] = (T)acc[c];
+}
+
 template <typename T>
 __global__ void diagonal_qp_kernel(T* __restrict__ dg, const T* __restrict__ ed, const T* __restrict__ md, int pm,
                                    const double* __restrict__ tab, int p, int q, Geom g) {
@@ -313,11 +382,17 @@ __global__ void diagonal_qp_kernel(T* __restrict__ dg, const T* __restrict__ ed,
 }
 
 int launch_diagonal(const pa_op* op, void* d, int constrained) {
-    if (op->mat == PA_MAT_ANISO) return fail(PA_EUNSUPPORTED, "diagonal of anisotropic material data is not built");
     if (op->geo != PA_GEOM_AFFINE) return fail(PA_EUNSUPPORTED, "diagonal of non-affine geometry is not built");
     const Geom g = make_geom(op->mesh, op->p, constrained != 0);
     const int nb = (g.Nn + 255) / 256;
-    if (op->mat == PA_MAT_QP_ISO) {
+    if (op->mat == PA_MAT_ANISO) {
+        if (op->dtype == PA_F64)
+            hipLaunchKernelGGL(diagonal_aniso_kernel<double>, dim3(nb), dim3(256), 0, op->stream, (double*)d,
+                               (const double*)op->ed, (const double*)op->md, op->d_tab, op->p, op->q, g);
+        else
+            hipLaunchKernelGGL(diagonal_aniso_kernel<float>, dim3(nb), dim3(256), 0, op->stream, (float*)d,
+                               (const float*)op->ed, (const float*)op->md, op->d_tab, op->p, op->q, g);
+    } else if (op->mat == PA_MAT_QP_ISO) {
         const int pm = op->md_point_major ? 1 : 0;
         if (op->dtype == PA_F64)
             hipLaunchKernelGGL(diagonal_qp_kernel<double>, dim3(nb), dim3(256), 0, op->stream, (double*)d,

@@ -202,11 +202,9 @@ def test_material_errors():
         pa.Operator.with_material(mesh, 2, 7, good)
     assert ei.value.code == pa.capi.PA_EINVAL
     op = pa.Operator.with_material(mesh, 2, pa.PA_MAT_ANISO, good)
-    for call in (lambda: op.diagonal(), lambda: op.hierarchy(),
-                 lambda: op.apply_variant(op.empty().zero_(), variant=pa.capi.PA_VARIANT_UNFUSED_SF)):
-        with pytest.raises(pa.PaError) as ei:
-            call()
-        assert ei.value.code == pa.capi.PA_EUNSUPPORTED
+    with pytest.raises(pa.PaError) as ei:
+        op.apply_variant(op.empty().zero_(), variant=pa.capi.PA_VARIANT_UNFUSED_SF)
+    assert ei.value.code == pa.capi.PA_EUNSUPPORTED
     # per-point Lame data: the hierarchy needs a coarser level than the finest
     qpop = pa.Operator.with_material(syn.BoxMesh(n=(3, 2, 2), clamped_faces=1), 1, pa.PA_MAT_QP_ISO,
                                      np.ones((12, 27, 2)))
@@ -232,17 +230,19 @@ def test_material_single_element(p, kind):
 
 
 @pytest.mark.parametrize("p", [1, 2, 3, 4, 8])
+@pytest.mark.parametrize("kind", [1, 2])
 @pytest.mark.parametrize("dtype", [0, 1])
-def test_qp_diagonal_parity(p, dtype):
-    """Diagonal with per-point Lame data (the Jacobi smoother's diagonal) vs the oracle's
-    element matrices; both layouts of the data (point-major at p = 1)."""
+def test_material_diagonal_parity(p, kind, dtype):
+    """Diagonal with general material data (the Jacobi smoother's diagonal) vs the oracle's
+    element matrices: per-point Lame data in both layouts (point-major at p = 1), and the
+    anisotropic Voigt stiffness."""
     pa = _pa()
-    print(f"per-point diagonal p={p} dtype={dtype}", flush=True)
+    print(f"material diagonal p={p} kind={kind} dtype={dtype}", flush=True)
     mesh = _mesh(p, seed=60 + p) if p < 8 else syn.BoxMesh(n=(2, 1, 1), L=(1.0, 0.6, 0.7), A=syn.SHEAR_A,
                                                             clamped_faces=0b000001)
     NE, q = mesh.num_elements, p + 2
-    data, C = _material(pa.PA_MAT_QP_ISO, NE, q, seed=p)
-    op = pa.Operator.with_material(mesh, p, pa.PA_MAT_QP_ISO, data, dtype=dtype)
+    data, C = _material(kind, NE, q, seed=p)
+    op = pa.Operator.with_material(mesh, p, kind, data, dtype=dtype)
     ref = material.GeneralOperator(mesh, p, q, C)
     for flags, constrained in ((0, True), (pa.PA_UNCONSTRAINED, False)):
         d = op.diagonal(flags)
@@ -251,10 +251,10 @@ def test_qp_diagonal_parity(p, dtype):
         assert _rel(d.double().cpu().numpy(), want) <= TOL[dtype], flags
 
 
-def _qp_problem(p, seed):
+def _qp_problem(p, seed, kind=1):
     """A clamped box whose hierarchy has a coarser level, with per-point Lame data that
     varies by +-40% inside every element around its element material (two materials,
-    E = 1 and 100, below p = 4)."""
+    E = 1 and 100, below p = 4), or (kind 2) a random anisotropic stiffness per element."""
     mesh = {1: syn.BoxMesh(n=(4, 4, 4), L=(2.0, 1.0, 1.0), A=syn.SHEAR_A, clamped_faces=1),
             2: syn.graded_mesh((4, 2, 2), seed=seed, L=(2.0, 1.0, 1.0), clamped_faces=1),
             4: syn.graded_mesh((3, 2, 2), seed=seed, L=(1.5, 1.0, 1.0), clamped_faces=1)}[p]
@@ -263,24 +263,32 @@ def _qp_problem(p, seed):
         lam_e, mu_e = syn.two_material_lame(NE, seed=seed)
     else:   # one base material: a residual of 1e-10 stays within FP64 reach at p = 4
         lam_e, mu_e = (np.full(NE, v) for v in syn.lame_from_young_poisson(1.0, 0.3))
+    b = elasticity.body_force_vector(mesh, p, q, (0.1, -0.2, -1.0))
+    if kind == 2:   # a general anisotropic stiffness per element around E = 1, nu = 0.3
+        lam0, mu0 = syn.lame_from_young_poisson(1.0, 0.3)
+        C = syn.random_spd_stiffness(NE, seed=seed + 2, lam=float(lam0), mu=float(mu0), spread=1.0)
+        ref = material.GeneralOperator(mesh, p, q, C)
+        b[ref.ess] = 0.0
+        return mesh, material.packed_upper(C), ref, b
     lam, mu = syn.quadrature_point_lame(lam_e, mu_e, q, seed=seed + 1, spread=0.4)
     ref = material.GeneralOperator(mesh, p, q, material.isotropic_voigt(lam, mu))
-    b = elasticity.body_force_vector(mesh, p, q, (0.1, -0.2, -1.0))
     b[ref.ess] = 0.0
     return mesh, np.stack([lam, mu], axis=-1), ref, b
 
 
 @pytest.mark.parametrize("p", [1, 2, 4])
 @pytest.mark.parametrize("mode", [0, 1, 2])
-def test_qp_material_solve_vs_direct(p, mode):
-    """GMG-PCG with per-point Lame data on the finest level (coarser levels take the
-    quadrature-weighted element means): the solution of the constrained system vs a dense
+@pytest.mark.parametrize("kind", [1, 2])
+def test_material_solve_vs_direct(p, mode, kind):
+    """GMG-PCG with general material data on the finest level (coarser levels take the
+    quadrature-weighted element means of per-point data, or the trace-matched isotropic
+    stiffness of an anisotropic C): the solution of the constrained system vs a dense
     direct solve of the oracle's assembled matrix, in all three solver modes."""
     pa = _pa()
-    print(f"per-point material solve p={p} mode={mode}", flush=True)
-    mesh, data, ref, b = _qp_problem(p, seed=30 + p)
+    print(f"material solve p={p} mode={mode} kind={kind}", flush=True)
+    mesh, data, ref, b = _qp_problem(p, seed=30 + p, kind=kind)
     u = solvers.solve_dense(ref.dense(True), b)
-    op = pa.Operator.with_material(mesh, p, pa.PA_MAT_QP_ISO, data)
+    op = pa.Operator.with_material(mesh, p, kind, data)
     x, info, rc = op.solve(torch.tensor(b, device="cuda"), rtol=1e-10, mode=mode, stop=1, cheb_degree=3,
                            h_levels=1 if p == 1 else 0)
     assert rc == 0, (rc, info.iters)
