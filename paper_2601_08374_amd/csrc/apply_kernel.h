@@ -847,19 +847,32 @@ pa_skeleton_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __restri
     const bool cl = g.clamp && clamped_node(g.clamp, gx, gy, gz, g);
     T acc[3] = {T(0), T(0), T(0)};
     if (!cl) {
-        // fixed summation order (z, y, x candidates), all loads independent
+        // fixed summation order (z, y, x candidates).  The loads of every existing candidate
+        // are issued before the first sum, so that their latencies overlap; a candidate
+        // that does not exist contributes zero.
+        T v[8][3];
 #pragma unroll
-        for (int kz = 0; kz < 2; ++kz)
+        for (int k = 0; k < 8; ++k) {
+            const int kx = k & 1, ky = (k >> 1) & 1, kz = k >> 2;
 #pragma unroll
-            for (int ky = 0; ky < 2; ++ky)
+            for (int c = 0; c < 3; ++c) v[k][c] = T(0);
+            if (nc.v[0][kx] && nc.v[1][ky] && nc.v[2][kz]) {
+                const int e = nc.e[0][kx] + g.nx * (nc.e[1][ky] + g.ny * nc.e[2][kz]);
+                const int s = SK::index(nc.l[0][kx], nc.l[1][ky], nc.l[2][kz]);
 #pragma unroll
-                for (int kx = 0; kx < 2; ++kx) {
-                    if (!(nc.v[0][kx] && nc.v[1][ky] && nc.v[2][kz])) continue;
-                    const int e = nc.e[0][kx] + g.nx * (nc.e[1][ky] + g.ny * nc.e[2][kz]);
-                    const int s = SK::index(nc.l[0][kx], nc.l[1][ky], nc.l[2][kz]);
+                for (int c = 0; c < 3; ++c) v[k][c] = sk[SK::offset(e, c, s, g.NE)];
+            }
+        }
+        // (an empty asm per value keeps the sums out of the branches above, which would
+        // otherwise wait for each candidate's loads before issuing the next one's)
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) acc[c] += sk[SK::offset(e, c, s, g.NE)];
-                }
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) asm volatile("" : "+v"(v[k][c]));
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[c] += v[k][c];
     } else {
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc[c] = x[c * NN + node];
