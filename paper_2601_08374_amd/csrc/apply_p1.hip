@@ -466,19 +466,31 @@ pa_lin_skeleton_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __re
     const bool cl = g.clamp && clamped_node(g.clamp, gx, gy, gz, g);
     T acc[3] = {T(0), T(0), T(0)};
     if (!cl) {
+        // fixed order (z, y, x candidates); every existing tile's loads are issued before the
+        // first sum, a tile that does not exist contributes zero
+        T v[8][3];
 #pragma unroll
-        for (int kz = 0; kz < 2; ++kz)
+        for (int k = 0; k < 8; ++k) {
+            const int kx = k & 1, ky = (k >> 1) & 1, kz = k >> 2;
 #pragma unroll
-            for (int ky = 0; ky < 2; ++ky)
+            for (int c = 0; c < 3; ++c) v[k][c] = T(0);
+            if (v_[0][kx] && v_[1][ky] && v_[2][kz]) {
+                const int tx = t_[0][kx], ty = t_[1][ky], tz = t_[2][kz];
+                const int t = tx + ntx * (ty + nty * tz);
 #pragma unroll
-                for (int kx = 0; kx < 2; ++kx) {
-                    if (!(v_[0][kx] && v_[1][ky] && v_[2][kz])) continue;
-                    const int tx = t_[0][kx], ty = t_[1][ky], tz = t_[2][kz];
-                    const int t = tx + ntx * (ty + nty * tz);
+                for (int c = 0; c < 3; ++c)
+                    v[k][c] = sk[lin_slot(t, c, gz - tz * TZ, gy - ty * kLinTY, gx - tx * kLinTX, TZ)];
+            }
+        }
+        // (an empty asm per value keeps the sums out of the branches above)
 #pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        acc[c] += sk[lin_slot(t, c, gz - tz * TZ, gy - ty * kLinTY, gx - tx * kLinTX, TZ)];
-                }
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) asm volatile("" : "+v"(v[k][c]));
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[c] += v[k][c];
     } else {
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc[c] = x[c * NN + node];
