@@ -348,14 +348,21 @@ struct ApplyCfg {
                       L.ST >= 2 * L.RC + (D - 1) * L.RZ + (Q - 1) * L.RY + Q,
                   "Ra strides overlap");
     static constexpr int LDS_ELEM = ST + UT + kEdStride;
+    // Lane utilisation of a sweep over n lines (one lane each) in 64-wide waves.
+    static constexpr double util(int n) { return double(n) / (((n + 63) / 64) * 64); }
+    // Score of E elements per workgroup: the utilisation of the column passes (forward Z,
+    // pointwise, backward Z: the bulk of the work); in single precision also a quarter
+    // weight for the mean of the X and Y line passes.  (Measured: the larger workgroups
+    // this picks at p = 2, 3 and 8 gain 2-8% in FP32; in FP64 p = 2 was unchanged and
+    // p = 3 slower, so FP64 keeps the smallest workgroup with the best column use.)
     static constexpr int pickE() {
+        constexpr bool lines = sizeof(T) == 4;
         int bestE = 1;
         double bestU = 0.0;
         for (int E = 1; E * QQ <= 256; ++E) {
             if (E > 1 && E * LDS_ELEM * (int)sizeof(T) > 65536) break;
-            int nt = ((E * QQ + 63) / 64) * 64;
-            double u = double(E * QQ) / nt;
-            if (u > bestU + 0.02) { bestU = u; bestE = E; }
+            const double u = util(E * QQ) + (lines ? 0.25 * 0.5 * (util(E * D * D) + util(E * D * Q)) : 0.0);
+            if (u > bestU + (lines ? 0.005 : 0.02)) { bestU = u; bestE = E; }
         }
         return bestE;
     }
