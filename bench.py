@@ -108,6 +108,63 @@ def cpu_baseline(ps, budget_s: float = 25.0):
             "per_p": res}
 
 
+def _sub_box(mesh, f: int = 4):
+    """The first 1/f^3 of a box (n // f elements per axis, same element size): the bounded
+    sample the oracle of a general form is timed on."""
+    import synthetic as syn
+    n = tuple(max(1, k // f) for k in mesh.n)
+    L = tuple(mesh.L[a] * n[a] / mesh.n[a] for a in range(3))
+    return syn.BoxMesh(n=n, L=L, A=mesh.A, x0=mesh.x0)
+
+
+def _oracle_rate(build, N: int):
+    """GDoF/s of one FP64 oracle apply (setup excluded) of a sample with N dofs."""
+    import synthetic as syn
+    op = build()
+    x = syn.uniform_vector(N, 0)
+    t0 = time.perf_counter()
+    op.apply(x)
+    t = time.perf_counter() - t0
+    return {"gdofs": N / t / 1e9, "t_apply_s": round(t, 4), "N": N}
+
+
+def cpu_baseline_forms(section: str, ps=(1, 2, 4, 8)):
+    """The FP64 oracle of one general form (material data, trilinear geometry, unstructured
+    mesh) timed on the host cores, at each p on the first 1/64 of the sheared box: the
+    same inputs as the GPU section of that name, restricted to the sample."""
+    import synthetic as syn
+    from oracle import geometry, material
+    notes = {"material": "material (strain-displacement form)",
+             "geometry": "trilinear-geometry (quadrature sum with per-point Jacobians)",
+             "unstructured": "unstructured-mesh (quadrature sum, explicit map)"}
+    out = {"kind": "oracle", "cores": len(os.sched_getaffinity(0)), "unit": "GDoF/s",
+           "sample": f"one FP64 {notes[section]} oracle apply at each p on the first 1/64 of the sheared "
+                     "box (n // 4 elements per axis, same element size), setup excluded"}
+    for p in ps:
+        mesh = syn.sheared_box_mesh(p)
+        NE, q = mesh.num_elements, p + 2
+        lam, mu = syn.two_material_lame(NE, seed=1)
+        sub = _sub_box(mesh)
+        ns = sub.num_elements
+        if section == "material":
+            C = syn.random_spd_stiffness(NE, seed=5)[:ns]
+            Cs = material.isotropic_voigt(*syn.quadrature_point_lame(lam[:ns], mu[:ns], q, seed=4))
+            out[f"p{p}"] = {"qpoint_iso": _oracle_rate(lambda: material.GeneralOperator(sub, p, q, Cs),
+                                                       sub.num_dofs(p)),
+                            "anisotropic": _oracle_rate(lambda: material.GeneralOperator(sub, p, q, C),
+                                                        sub.num_dofs(p))}
+        elif section == "geometry":
+            sv = syn.perturbed_vertices(sub, amp=0.2, seed=17)
+            out[f"p{p}"] = _oracle_rate(lambda: geometry.TrilinearOperator(sub, p, q, sv, lam[:ns], mu[:ns]),
+                                        sub.num_dofs(p))
+        else:
+            sv = syn.perturbed_vertices(sub, amp=0.2, seed=17)
+            hsub, _, osub = syn.box_as_unstructured(sub, sv, p, seed=1, permute=False, renumber=False)
+            out[f"p{p}"] = _oracle_rate(lambda: geometry.UnstructuredOperator(hsub, q, lam[osub], mu[osub]),
+                                        hsub.num_dofs)
+    return out
+
+
 def measured_ceilings(torch, dev, reps: int = 5):
     """Attainable rates measured on the device: vector FMA throughput in FP64 and FP32
     (pa_probe_fma, 8 independent chains per lane) and a plain 1 GiB device-to-device copy
@@ -353,15 +410,15 @@ def main(argv=None):
     if not args.no_material:
         log("apply with general material data")
         from paper_2601_08374_amd import benchmarks
-        result["material"] = benchmarks.apply_material(torch, dev, oracle=not args.no_cpu_baseline)
+        result["material"] = benchmarks.apply_material(torch, dev)
     if not args.no_geometry:
         log("apply on non-affine geometry")
         from paper_2601_08374_amd import benchmarks
-        result["geometry"] = benchmarks.apply_geometry(torch, dev, oracle=not args.no_cpu_baseline)
+        result["geometry"] = benchmarks.apply_geometry(torch, dev)
     if not args.no_unstructured:
         log("apply on unstructured meshes")
         from paper_2601_08374_amd import benchmarks
-        result["unstructured"] = benchmarks.apply_unstructured(torch, dev, oracle=not args.no_cpu_baseline)
+        result["unstructured"] = benchmarks.apply_unstructured(torch, dev)
     if not args.no_solve:
         log("cantilever solves")
         from paper_2601_08374_amd import benchmarks
@@ -374,6 +431,10 @@ def main(argv=None):
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(STEP_PS)
+        for section in ("material", "geometry", "unstructured"):
+            if section in result:
+                log(f"cpu baseline (oracle), {section}")
+                result[section]["cpu_oracle"] = cpu_baseline_forms(section)
     print(json.dumps(result), flush=True)
     return 0
 

@@ -141,46 +141,17 @@ def _time_apply(torch, dev, op, reps):
     return e0.elapsed_time(e1) * 1e-3 / reps
 
 
-def _sub_box(mesh, f=4):
-    """The first 1/f^3 of a box (n // f per axis) with the same element size: the bounded
-    sample the CPU oracle is timed on."""
-    import synthetic as syn
-    n = tuple(max(1, k // f) for k in mesh.n)
-    L = tuple(mesh.L[a] * n[a] / mesh.n[a] for a in range(3))
-    return syn.BoxMesh(n=n, L=L, A=mesh.A, x0=mesh.x0)
-
-
-def _oracle_rate(build, N):
-    """GDoF/s of one FP64 oracle apply (setup excluded) of a sample with N dofs."""
-    import synthetic as syn
-    op = build()
-    x = syn.uniform_vector(N, 0)
-    t0 = time.perf_counter()
-    op.apply(x)
-    t = time.perf_counter() - t0
-    return {"gdofs": N / t / 1e9, "t_apply_s": round(t, 4), "N": N}
-
-
-def _cpu_note(section):
-    import os
-    return {"kind": "oracle", "cores": len(os.sched_getaffinity(0)), "unit": "GDoF/s",
-            "sample": f"one FP64 {section} oracle apply at each p on the first 1/64 of the sheared box "
-                      "(n // 4 elements per axis, same element size), setup excluded"}
-
-
-def apply_material(torch, dev, ps=(1, 2, 4, 8), reps=10, oracle=True):
+def apply_material(torch, dev, ps=(1, 2, 4, 8), reps=10):
     """The fused apply with the three material data forms on the sheared box (q = p+2):
     per-element Lame parameters, per-quadrature-point Lame parameters and a per-element
     anisotropic Voigt stiffness; HIP-event time per apply, FP64 and FP32, with rates
-    against the VALU and HBM peaks, and the FP64 oracle timed on the host cores."""
+    against the VALU and HBM peaks."""
     import synthetic as syn
     import paper_2601_08374_amd as pa
-    from oracle import material
     out = {"workload": "sheared box (~4.2M dofs), q=p+2; two materials (element), +-30% per point "
                        f"(quadrature point), random SPD Voigt stiffness (anisotropic); mean of {reps} "
                        "applies after one warm-up, HIP events",
            "extra_point_flops": {k: v for k, v in EXTRA_POINT_FLOPS.items() if k != "trilinear"}}
-    cpu = _cpu_note("material (strain-displacement form)")
     for p in ps:
         mesh = syn.sheared_box_mesh(p)
         NE, q = mesh.num_elements, p + 2
@@ -204,34 +175,21 @@ def apply_material(torch, dev, ps=(1, 2, 4, 8), reps=10, oracle=True):
                 rec[f"{form}_{dname}"] = _rates(op.N, NE, p, word, dname, t, extra_words=xw, extra_flops_pt=xf)
                 op.close()
         out[f"p{p}"] = rec
-        if oracle:
-            sub = _sub_box(mesh)
-            ns = sub.num_elements
-            Cs = material.isotropic_voigt(*syn.quadrature_point_lame(lam[:ns], mu[:ns], q, seed=4))
-            cpu[f"p{p}"] = {"qpoint_iso": _oracle_rate(lambda: material.GeneralOperator(sub, p, q, Cs),
-                                                       sub.num_dofs(p)),
-                            "anisotropic": _oracle_rate(lambda: material.GeneralOperator(sub, p, q, C[:ns]),
-                                                        sub.num_dofs(p))}
-            del Cs
         del qp, C, c21
         torch.cuda.empty_cache()
-    if oracle:
-        out["cpu_oracle"] = cpu
     return out
 
 
-def apply_geometry(torch, dev, ps=(1, 2, 4, 8), reps=10, oracle=True):
+def apply_geometry(torch, dev, ps=(1, 2, 4, 8), reps=10):
     """The fused apply on the sheared box with its interior vertices moved (trilinear
     hexahedra): geometry stored per quadrature point (J^{-1}, w det J) vs recomputed per
     point from 21 map coefficients per element, next to the affine box; HIP-event time
-    per apply, FP64 and FP32, rates against the peaks, and the FP64 oracle on the host."""
+    per apply, FP64 and FP32, and rates against the peaks."""
     import synthetic as syn
     import paper_2601_08374_amd as pa
-    from oracle import geometry
     out = {"workload": "sheared box (~4.2M dofs), q=p+2, two materials; interior vertices moved by up to "
                        f"0.2 of the spacing (seed 17); mean of {reps} applies after one warm-up, HIP events",
            "extra_point_flops": {"trilinear": EXTRA_POINT_FLOPS["trilinear"]}}
-    cpu = _cpu_note("trilinear-geometry (quadrature sum with per-point Jacobians)")
     for p in ps:
         mesh = syn.sheared_box_mesh(p)
         NE, q = mesh.num_elements, p + 2
@@ -253,32 +211,21 @@ def apply_geometry(torch, dev, ps=(1, 2, 4, 8), reps=10, oracle=True):
                 rec[f"{form}_{dname}"] = _rates(op.N, NE, p, word, dname, t, extra_words=xw, extra_flops_pt=xf)
                 op.close()
         out[f"p{p}"] = rec
-        if oracle:
-            sub = _sub_box(mesh)
-            sv = syn.perturbed_vertices(sub, amp=0.2, seed=17)
-            ns = sub.num_elements
-            cpu[f"p{p}"] = _oracle_rate(lambda: geometry.TrilinearOperator(sub, p, q, sv, lam[:ns], mu[:ns]),
-                                        sub.num_dofs(p))
         torch.cuda.empty_cache()
-    if oracle:
-        out["cpu_oracle"] = cpu
     return out
 
 
-def apply_unstructured(torch, dev, ps=(1, 2, 4, 8), reps=10, oracle=True):
+def apply_unstructured(torch, dev, ps=(1, 2, 4, 8), reps=10):
     """The fused apply on the distorted sheared box given as an unstructured mesh
     (explicit element-to-node map, every element in a random orientation), in box order
     and with elements and nodes shuffled at random (no locality), next to the structured
     trilinear operator on the same geometry; HIP-event time per apply, rates against the
-    peaks (algorithmic bytes add the map, 4 (p+1)^3 bytes per element), and the FP64
-    oracle on the host."""
+    peaks (algorithmic bytes add the map, 4 (p+1)^3 bytes per element)."""
     import synthetic as syn
     import paper_2601_08374_amd as pa
-    from oracle import geometry
     out = {"workload": "sheared box (~4.2M dofs), q=p+2, two materials, interior vertices moved by up to 0.2 "
                        "of the spacing; unstructured: random orientation per element, box order ('ordered') or "
                        f"random element and node order ('shuffled'); mean of {reps} applies after one warm-up"}
-    cpu = _cpu_note("unstructured-mesh (quadrature sum, explicit map)")
     for p in ps:
         mesh = syn.sheared_box_mesh(p)
         NE = mesh.num_elements
@@ -306,15 +253,7 @@ def apply_unstructured(torch, dev, ps=(1, 2, 4, 8), reps=10, oracle=True):
                 op.close()
         out[f"p{p}"] = rec
         del hm, hs
-        if oracle:
-            sub = _sub_box(mesh)
-            sv = syn.perturbed_vertices(sub, amp=0.2, seed=17)
-            hsub, _, osub = syn.box_as_unstructured(sub, sv, p, seed=1, permute=False, renumber=False)
-            cpu[f"p{p}"] = _oracle_rate(lambda: geometry.UnstructuredOperator(hsub, p + 2, lam[osub], mu[osub]),
-                                        hsub.num_dofs)
         torch.cuda.empty_cache()
-    if oracle:
-        out["cpu_oracle"] = cpu
     return out
 
 
