@@ -49,3 +49,21 @@ def test_bench_imports_the_oracle_only_in_its_cpu_baseline_leg():
 def test_graft_entry_imports_the_oracle_only_in_smoke():
     hits = _oracle_imports(os.path.join(ROOT, "__graft_entry__.py"))
     assert {func for _, func in hits} <= {"smoke"}
+
+
+def test_missing_library_fails_loudly():
+    """With no built library the binding raises; there is no fallback path to run instead."""
+    import subprocess
+    import sys
+    env = dict(os.environ, PAELAST_LIB=os.path.join(ROOT, "no_such_dir", "libpaelast.so"))
+    code = ("import sys\n"
+            "from paper_2601_08374_amd import capi\n"
+            "try:\n"
+            "    capi.pa_elast_ndofs\n"
+            "except RuntimeError as e:\n"
+            "    print(e); sys.exit(3)\n"
+            "sys.exit(0)\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 3, r.stdout + r.stderr
+    assert "not built" in r.stdout
