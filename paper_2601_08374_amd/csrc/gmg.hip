@@ -488,7 +488,7 @@ int setup_gmg(pa_op* op, const pa_solve_opts_t* o, pa_gmg** out) {
             double* A = nullptr;
             double* col = nullptr;
             if (hipMalloc(&A, (size_t)G->Nc * G->Nc * sizeof(double)) != hipSuccess ||
-                hipMalloc(&col, (size_t)G->Nc * sizeof(double)) != hipSuccess) {
+                hipMalloc(&col, (size_t)coarse_invert_words(G->Nc) * sizeof(double)) != hipSuccess) {
                 (void)hipGetLastError();
                 if (A) (void)hipFree(A);
                 rc = fail(PA_ENOMEM, "coarse matrix allocation failed (%d dofs)", G->Nc);
@@ -788,7 +788,7 @@ int64_t bytes_required(const MeshDesc& md, int p, int dtype, int with_solver) {
                  (l + 1 < plan.size() ? 6 : 2) * n * (int64_t)vw + 65536;
     }
     const int64_t nc = dofs_of(plan.back().mesh, plan.back().p);
-    bytes += nc * nc * (int64_t)(sizeof(double) + vw);
+    bytes += nc * nc * (int64_t)(sizeof(double) + vw) + coarse_invert_words((int)nc) * (int64_t)sizeof(double);
     const int64_t n0 = dofs_of(md, p);
     bytes += 4 * n0 * (int64_t)vw;
     if (vt == PA_F32) bytes += n0 * 4 + 2 * n0 * 8 + (NE * kEdStride + skeleton_words(p, md.n)) * 8;

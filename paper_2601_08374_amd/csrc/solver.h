@@ -62,7 +62,11 @@ int launch_h_prolong(const void* xc, void* xf, const HAxis ax[3], const Geom& gc
 int launch_h_restrict(const void* rf, const void* tf, void* rc, const HAxis ax[3], const Geom& gc, const Geom& gf, int dtype,
                       hipStream_t s);
 int launch_coarse_assemble(double* A, int N, const pa_op* op, hipStream_t s);
-int coarse_invert(double* A, double* col, int N, hipStream_t s);
+// Blocked Gauss-Jordan inverse of the SPD coarse matrix in place; work holds
+// coarse_invert_words(N) doubles.
+constexpr int kGjNB = 32;
+int64_t coarse_invert_words(int N);
+int coarse_invert(double* A, double* work, int N, hipStream_t s);
 int launch_dense_cast(void* out, int dtype, const double* in, int64_t n, hipStream_t s);
 int launch_dense_matvec(const void* Ai, const void* x, void* y, int N, int dtype, hipStream_t s);
 

@@ -635,29 +635,121 @@ __global__ void coarse_constrain_kernel(double* __restrict__ A, int N, Geom g) {
     }
 }
 
-// Gauss-Jordan elimination step k on [A | X] stored in place (A becomes A^{-1}):
-// the SPD coarse matrix needs no pivoting.  Two kernels per step: scale the pivot
-// row (with the saved pivot column), then eliminate the other rows.
-__global__ void gj_save_col_kernel(const double* __restrict__ A, double* __restrict__ col, int N, int k) {
-    GRID_STRIDE(i, (int64_t)N) col[i] = A[(size_t)i * N + k];
-}
+// Blocked Gauss-Jordan inversion of the coarse matrix, in place (A becomes A^{-1}),
+// kGjNB pivots per block; the constrained coarse matrix is SPD, so no pivoting.  With K
+// the indices of a block, P = A[K,K] and Pi = P^{-1}, one block step is the scalar
+// elimination step applied to the block of pivots:
+//   A[i,j] <- A[i,j] - A[i,K] Pi A[K,j]   (i, j not in K)
+//   A[i,K] <- -A[i,K] Pi,   A[K,j] <- Pi A[K,j],   A[K,K] <- Pi.
+// Four kernels per block: save the column and row blocks, invert P in one workgroup,
+// form the new row block W = Pi A[K,:] (W[:,K] = Pi), then one rank-nb update of A.
 
-__global__ void gj_update_kernel(double* __restrict__ A, const double* __restrict__ col, int N, int k) {
-    // new row k: A[k][j] / piv (A[k][k] <- 1/piv); other rows: A[i][j] - col[i] * newrow[j]
-    const double piv = col[k];
-    GRID_STRIDE(t, (int64_t)N * N) {
-        const int i = (int)(t / N), j = (int)(t % N);
-        const double akj = (j == k) ? 1.0 / piv : A[(size_t)k * N + j] / piv;
-        if (i == k) continue;
-        const double aik = col[i];
-        const double aij = (j == k) ? 0.0 : A[t];
-        A[t] = aij - aik * akj;
+// C = A[:, K] (N x nb, row-major), R = A[K, :] (nb x N)
+__global__ void gjb_save_kernel(const double* __restrict__ A, double* __restrict__ C, double* __restrict__ R,
+                                int N, int k0, int nb) {
+    GRID_STRIDE(t, (int64_t)N * nb) {
+        const int i = (int)(t / nb), m = (int)(t % nb);
+        C[t] = A[(size_t)i * N + k0 + m];
+        R[(size_t)m * N + i] = A[(size_t)(k0 + m) * N + i];
     }
 }
 
-__global__ void gj_pivot_row_kernel(double* __restrict__ A, const double* __restrict__ col, int N, int k) {
-    const double piv = col[k];
-    GRID_STRIDE(j, (int64_t)N) A[(size_t)k * N + j] = (j == k) ? 1.0 / piv : A[(size_t)k * N + j] / piv;
+// Pi = P^{-1} for the nb x nb pivot block P = C[K rows], by scalar Gauss-Jordan in LDS
+// (one thread per entry).
+__global__ void __launch_bounds__(kGjNB * kGjNB)
+gjb_pivot_inverse_kernel(const double* __restrict__ C, double* __restrict__ Pi, int k0, int nb) {
+    __shared__ double P[kGjNB][kGjNB + 1];
+    __shared__ double colk[kGjNB];
+    const int i = threadIdx.y, j = threadIdx.x;
+    const bool in = i < nb && j < nb;
+    if (in) P[i][j] = C[(size_t)(k0 + i) * nb + j];
+    __syncthreads();
+    for (int k = 0; k < nb; ++k) {
+        if (in && j == 0) colk[i] = P[i][k];
+        __syncthreads();
+        double v = 0.0;
+        if (in) {
+            const double piv = colk[k];
+            const double akj = (j == k) ? 1.0 / piv : P[k][j] / piv;
+            v = (i == k) ? akj : ((j == k) ? 0.0 : P[i][j]) - colk[i] * akj;
+        }
+        __syncthreads();
+        if (in) P[i][j] = v;
+        __syncthreads();
+    }
+    if (in) Pi[i * nb + j] = P[i][j];
+}
+
+// W = Pi R (nb x N) with W[:, K] = Pi
+__global__ void gjb_rows_kernel(const double* __restrict__ Pi, const double* __restrict__ R, double* __restrict__ W,
+                                int N, int k0, int nb) {
+    GRID_STRIDE(t, (int64_t)nb * N) {
+        const int m = (int)(t / N), j = (int)(t % N);
+        double v = 0.0;
+        if (j >= k0 && j < k0 + nb) {
+            v = Pi[m * nb + (j - k0)];
+        } else {
+            for (int l = 0; l < nb; ++l) v = fma(Pi[m * nb + l], R[(size_t)l * N + j], v);
+        }
+        W[t] = v;
+    }
+}
+
+// Rank-nb update on 64 x 64 tiles (256 threads, 4 x 4 entries each):
+//   rows in K:      A[i,j] = W[i - k0, j]
+//   other rows:     A[i,j] = (j in K ? 0 : A[i,j]) - sum_m C[i,m] W[m,j]
+__global__ void __launch_bounds__(256)
+gjb_update_kernel(double* __restrict__ A, const double* __restrict__ C, const double* __restrict__ W, int N, int k0,
+                  int nb) {
+    __shared__ double Cs[64][kGjNB + 1];
+    __shared__ double Ws[kGjNB][64 + 1];
+    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < 64 * kGjNB; t += 256) {
+        const int r = t / kGjNB, m = t % kGjNB;
+        Cs[r][m] = (i0 + r < N && m < nb) ? C[(size_t)(i0 + r) * nb + m] : 0.0;
+    }
+    for (int t = tid; t < kGjNB * 64; t += 256) {
+        const int m = t / 64, c = t % 64;
+        Ws[m][c] = (j0 + c < N && m < nb) ? W[(size_t)m * N + j0 + c] : 0.0;
+    }
+    __syncthreads();
+    const int tr = tid / 16, tc = tid % 16;
+    double acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    for (int m = 0; m < kGjNB; ++m) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = Cs[tr + 16 * u][m];
+            b[u] = Ws[m][tc + 16 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int i = i0 + tr + 16 * u;
+        if (i >= N) continue;
+        const bool iK = i >= k0 && i < k0 + nb;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int j = j0 + tc + 16 * v;
+            if (j >= N) continue;
+            const size_t o = (size_t)i * N + j;
+            if (iK) {
+                A[o] = W[(size_t)(i - k0) * N + j];
+            } else {
+                const bool jK = j >= k0 && j < k0 + nb;
+                A[o] = (jK ? 0.0 : A[o]) - acc[u][v];
+            }
+        }
+    }
 }
 
 template <typename T>
@@ -981,12 +1073,20 @@ int launch_coarse_assemble(double* A, int N, const pa_op* op, hipStream_t s) {
     return PA_OK;
 }
 
-int coarse_invert(double* A, double* col, int N, hipStream_t s) {
-    const int g1 = grid_for(N), g2 = grid_for((int64_t)N * N);
-    for (int k = 0; k < N; ++k) {
-        hipLaunchKernelGGL(gj_save_col_kernel, dim3(g1), dim3(kBlock), 0, s, A, col, N, k);
-        hipLaunchKernelGGL(gj_update_kernel, dim3(g2), dim3(kBlock), 0, s, A, col, N, k);
-        hipLaunchKernelGGL(gj_pivot_row_kernel, dim3(g1), dim3(kBlock), 0, s, A, col, N, k);
+int64_t coarse_invert_words(int N) { return 3 * (int64_t)N * kGjNB + (int64_t)kGjNB * kGjNB; }
+
+int coarse_invert(double* A, double* work, int N, hipStream_t s) {
+    double* C = work;
+    double* R = C + (size_t)N * kGjNB;
+    double* W = R + (size_t)N * kGjNB;
+    double* Pi = W + (size_t)N * kGjNB;
+    const dim3 gu((N + 63) / 64, (N + 63) / 64);
+    for (int k0 = 0; k0 < N; k0 += kGjNB) {
+        const int nb = N - k0 < kGjNB ? N - k0 : kGjNB;
+        hipLaunchKernelGGL(gjb_save_kernel, dim3(grid_for((int64_t)N * nb)), dim3(kBlock), 0, s, A, C, R, N, k0, nb);
+        hipLaunchKernelGGL(gjb_pivot_inverse_kernel, dim3(1), dim3(kGjNB, kGjNB), 0, s, C, Pi, k0, nb);
+        hipLaunchKernelGGL(gjb_rows_kernel, dim3(grid_for((int64_t)nb * N)), dim3(kBlock), 0, s, Pi, R, W, N, k0, nb);
+        hipLaunchKernelGGL(gjb_update_kernel, gu, dim3(256), 0, s, A, C, W, N, k0, nb);
     }
     PA_CHECK_LAUNCH();
     return PA_OK;
