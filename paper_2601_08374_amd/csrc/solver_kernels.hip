@@ -720,6 +720,8 @@ gjb_update_kernel(double* __restrict__ A, const double* __restrict__ C, const do
     for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    // (a partial unroll: the full one hoists every LDS read and spills)
+#pragma unroll 4
     for (int m = 0; m < kGjNB; ++m) {
         double a[4], b[4];
 #pragma unroll
