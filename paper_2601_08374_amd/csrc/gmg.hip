@@ -271,7 +271,8 @@ int sync_scalars(pa_gmg* G) {
 }
 
 // lambda_max(D^{-1}A) by power iteration from a SplitMix64 vector (clamped entries
-// zeroed): w = A v, lambda = v.w / v.Dv, v <- D^{-1}w / |D^{-1}w|.
+// zeroed): w = A v, lambda = v.w / v.Dv, v <- D^{-1}w / |D^{-1}w|.  The normalisations
+// read their norms from the device scalars, so the host waits once, for the last lambda.
 int power_iteration(pa_gmg* G, int l, double* out) {
     Level& v = G->L[l];
     hipStream_t s = G->stream;
@@ -279,14 +280,11 @@ int power_iteration(pa_gmg* G, int l, double* out) {
     void* vv = v.r;
     void* w = v.t;
     void* z = v.d;
-    if ((rc = launch_splitmix(vv, v.dtype, G->opts.seed + (uint64_t)l, v.N, s))) return rc;
-    if ((rc = launch_set_clamped(vv, v.dtype, v.g, 0.0, s))) return rc;
-    if ((rc = launch_dot(vv, vv, nullptr, v.dtype, v.N, G->part, s))) return rc;
-    if ((rc = launch_dot_final(G->part, G->scal, FIN_STORE, S_T0, s))) return rc;
-    if ((rc = sync_scalars(G))) return rc;
-    if (!(G->hscal[S_T0] > 0.0)) return fail(PA_EINVAL, "level %d has no free dofs", l);
-    if ((rc = launch_axpby(vv, vv, 0.0, 1.0 / std::sqrt(G->hscal[S_T0]), v.dtype, v.N, s))) return rc;
-    double lam = 0.0;
+    if ((rc = launch_splitmix(z, v.dtype, G->opts.seed + (uint64_t)l, v.N, s))) return rc;
+    if ((rc = launch_set_clamped(z, v.dtype, v.g, 0.0, s))) return rc;
+    if ((rc = launch_dot(z, z, nullptr, v.dtype, v.N, G->part, s))) return rc;
+    if ((rc = launch_dot_final(G->part, G->scal, FIN_STORE, S_NB, s))) return rc;
+    if ((rc = launch_cast_scale(vv, v.dtype, z, v.dtype, G->scal, S_NB, 1, v.N, s))) return rc;
     for (int it = 0; it < G->opts.power_iters; ++it) {
         if ((rc = level_apply(v, vv, w))) return rc;
         if ((rc = launch_dot(vv, w, nullptr, v.dtype, v.N, G->part, s))) return rc;
@@ -296,12 +294,13 @@ int power_iteration(pa_gmg* G, int l, double* out) {
         if ((rc = launch_cheb_first(z, v.dinv, w, 1.0, v.dtype, v.N, s))) return rc;
         if ((rc = launch_dot(z, z, nullptr, v.dtype, v.N, G->part, s))) return rc;
         if ((rc = launch_dot_final(G->part, G->scal, FIN_STORE, S_NB, s))) return rc;
-        if ((rc = sync_scalars(G))) return rc;
-        lam = G->hscal[S_T0] / G->hscal[S_NR];
-        const double nz = std::sqrt(G->hscal[S_NB]);
-        if (!(nz > 0.0) || !std::isfinite(lam)) return fail(PA_EBREAKDOWN, "power iteration broke down on level %d", l);
-        if ((rc = launch_axpby(vv, z, 1.0 / nz, 0.0, v.dtype, v.N, s))) return rc;
+        if ((rc = launch_cast_scale(vv, v.dtype, z, v.dtype, G->scal, S_NB, 1, v.N, s))) return rc;
     }
+    if ((rc = sync_scalars(G))) return rc;
+    if (!(G->hscal[S_NR] > 0.0)) return fail(PA_EINVAL, "level %d has no free dofs", l);
+    const double lam = G->hscal[S_T0] / G->hscal[S_NR];
+    if (!(G->hscal[S_NB] > 0.0) || !std::isfinite(lam))
+        return fail(PA_EBREAKDOWN, "power iteration broke down on level %d", l);
     *out = lam;
     return PA_OK;
 }
