@@ -213,6 +213,30 @@ def test_coarse_solve_matches_direct():
     assert _rel(got, np.linalg.solve(A, b)) <= 1e-11
 
 
+@pytest.mark.parametrize("n", [(6, 5, 4), (10, 9, 8)])
+def test_coarse_inverse_several_blocks(n):
+    """The coarse inverse at sizes spanning many 32-pivot blocks with a ragged last block and
+    several 64 x 64 update tiles (630 and 2970 dofs): coarse solve vs a dense direct solve."""
+    pa = _pa()
+    mesh = syn.graded_mesh(n, seed=3, L=(1.2, 1.0, 0.9), A=syn.SHEAR_A, clamped_faces=1)
+    NE = mesh.num_elements
+    rng = np.random.default_rng(4)
+    lam, mu = rng.uniform(0.5, 2.0, NE), rng.uniform(0.5, 2.0, NE)
+    op = pa.Operator(mesh, 2, lam, mu)
+    H = op.hierarchy(h_levels=0)
+    lv = _oracle_levels(mesh, 2, lam, mu, 0)
+    oop = lv[-1][2]
+    assert H.num_levels == 2 and H.level_info(1)["N"] == oop.N
+    assert oop.N % 32 != 0 and oop.N > 2 * 64
+    A = oop.dense(True)
+    b = syn.uniform_vector(oop.N, 8)
+    b[oop.ess] = 0
+    got = _np(H.coarse_solve(torch.tensor(b, device="cuda")))
+    assert _rel(got, np.linalg.solve(A, b)) <= 1e-10
+    H.close()
+    op.close()
+
+
 @pytest.mark.parametrize("p,n_h", [(4, 1), (2, 2), (3, 1)])
 def test_vcycle_matches_oracle(p, n_h):
     pa, mesh, op, H, lv, lhat = _small_setup(p=p, n_h=n_h)
