@@ -104,7 +104,7 @@ typedef struct pa_solve_opts_t {
     double cheb_lo_frac;      /* smoothing interval [lo_frac*lmax, lmax]                       */
     double cheb_safety;       /* lmax = safety * estimate                                      */
     int max_iter;             /* outer PCG iteration cap (Sec. 3.2: 5000)                      */
-    double inner_rtol;        /* PA_SOLVE_F32_IR: inner FP32 PCG tolerance                     */
+    double inner_rtol;        /* PA_SOLVE_F32_IR: inner FP32 PCG tolerance (default 3e-3)      */
     int inner_max_iter;       /* PA_SOLVE_F32_IR: inner iteration cap                          */
     int max_outer;            /* PA_SOLVE_F32_IR: refinement step cap                          */
     uint64_t seed;            /* power-iteration start vector (SplitMix64 stream)              */
