@@ -223,6 +223,9 @@ def main(argv=None):
     ap.add_argument("--profile-solve", type=int, default=0, metavar="P",
                     help="profiling mode: build the degree-P cantilever hierarchy, run one GMG-PCG solve "
                          "(--solve-mode) to rtol 1e-8 and exit")
+    ap.add_argument("--profile-setup", action="store_true",
+                    help="profiling mode: build the FP64 GMG hierarchy (Chebyshev(3), automatic h-levels) of "
+                         "three serving-sized boxes --reps times each, print the setup times and exit")
     ap.add_argument("--solve-mode", choices=("f64", "f32_ir", "f32_prec"), default="f64")
     ap.add_argument("--dtype", choices=("f64", "f32"), default="f64")
     ap.add_argument("--reps", type=int, default=10)
@@ -289,6 +292,28 @@ def main(argv=None):
         print(json.dumps({"profile_solve": p, "mode": args.solve_mode, "rc": rc, "iters": info.iters,
                           "outer": info.outer_iters, "rel_res_true": info.rel_res_true, "solve_s": t,
                           "N": op.N}), flush=True)
+        return 0
+
+    if args.profile_setup:
+        out = []
+        for n, p in (((9, 9, 9), 2), ((17, 25, 30), 4), ((32, 32, 32), 8)):
+            mesh = syn.BoxMesh(n=n, L=tuple(v / 32 for v in n), clamped_faces=1)
+            NE = mesh.num_elements
+            lam, mu = (float(v) for v in syn.lame_from_young_poisson(10.0, 0.3))
+            op = pa.Operator(mesh, p, np.full(NE, lam), np.full(NE, mu))
+            ts = []
+            for _ in range(args.reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                H = op.hierarchy(mode=pa.PA_SOLVE_F64, stop=pa.PA_STOP_TRUE, cheb_degree=3)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+                nc = H.level_info(H.num_levels - 1)["N"]
+                H.close()
+            op.close()
+            out.append({"n": n, "p": p, "N": op.N, "coarse_N": nc, "setup_ms_min": round(1e3 * min(ts), 2),
+                        "setup_ms_median": round(1e3 * float(np.median(ts)), 2)})
+        print(json.dumps({"profile_setup": out, "reps": args.reps}), flush=True)
         return 0
 
     # ---------------- timed step: FP64 apply at every p of the sweep
