@@ -287,18 +287,15 @@ int power_iteration(pa_gmg* G, int l, double* out) {
     if ((rc = launch_cast_scale(vv, v.dtype, z, v.dtype, G->scal, S_NB, 1, v.N, s))) return rc;
     for (int it = 0; it < G->opts.power_iters; ++it) {
         if ((rc = level_apply(v, vv, w))) return rc;
-        if ((rc = launch_dot(vv, w, nullptr, v.dtype, v.N, G->part, s))) return rc;
+        // z = D^{-1} w with v.w -> S_T0, v.Dv -> S_T1 and z.z -> S_NB, in one pass
+        if ((rc = launch_power_pass(vv, w, v.dinv, z, v.dtype, v.N, G->part, s))) return rc;
         if ((rc = launch_dot_final(G->part, G->scal, FIN_STORE, S_T0, s))) return rc;
-        if ((rc = launch_vdv(vv, v.dinv, v.dtype, v.N, G->part, s))) return rc;
-        if ((rc = launch_dot_final(G->part, G->scal, FIN_STORE, S_NR, s))) return rc;
-        if ((rc = launch_cheb_first(z, v.dinv, w, 1.0, v.dtype, v.N, s))) return rc;
-        if ((rc = launch_dot(z, z, nullptr, v.dtype, v.N, G->part, s))) return rc;
-        if ((rc = launch_dot_final(G->part, G->scal, FIN_STORE, S_NB, s))) return rc;
+        if ((rc = launch_dot_final(G->part + 2 * kReduceBlocks, G->scal, FIN_STORE, S_NB, s))) return rc;
         if ((rc = launch_cast_scale(vv, v.dtype, z, v.dtype, G->scal, S_NB, 1, v.N, s))) return rc;
     }
     if ((rc = sync_scalars(G))) return rc;
-    if (!(G->hscal[S_NR] > 0.0)) return fail(PA_EINVAL, "level %d has no free dofs", l);
-    const double lam = G->hscal[S_T0] / G->hscal[S_NR];
+    if (!(G->hscal[S_T1] > 0.0)) return fail(PA_EINVAL, "level %d has no free dofs", l);
+    const double lam = G->hscal[S_T0] / G->hscal[S_T1];
     if (!(G->hscal[S_NB] > 0.0) || !std::isfinite(lam))
         return fail(PA_EBREAKDOWN, "power iteration broke down on level %d", l);
     *out = lam;
@@ -455,7 +452,7 @@ int setup_gmg(pa_op* op, const pa_solve_opts_t* o, pa_gmg** out) {
             }
         }
         if (rc) break;
-        if (hipMalloc(&G->part, 2 * kReduceBlocks * sizeof(double)) != hipSuccess ||
+        if (hipMalloc(&G->part, 4 * kReduceBlocks * sizeof(double)) != hipSuccess ||
             hipMalloc(&G->scal, S_COUNT * sizeof(double)) != hipSuccess ||
             hipHostMalloc(&G->hscal, S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess ||
             hipEventCreateWithFlags(&G->ev, hipEventDisableTiming) != hipSuccess) {

@@ -35,6 +35,10 @@ int launch_dot(const void* a, const void* b, const void* c, int dtype, int64_t n
 int launch_dot_final(const double* part, double* scal, int op, int slot, hipStream_t s);
 int launch_pcg_init(const double* part, double* scal, double rtol, int stop, hipStream_t s);
 int launch_vdv(const void* v, const void* dinv, int dtype, int64_t n, double* part, hipStream_t s);
+// Power-iteration pass: z = dinv w and the stage-1 sums of v.w, v.Dv (part, part + nb) and z.z
+// (part + 2 nb, with zeros at part + 3 nb); part holds 4 kReduceBlocks doubles.
+int launch_power_pass(const void* v, const void* w, const void* dinv, void* z, int dtype, int64_t n, double* part,
+                      hipStream_t s);
 int launch_pcg_xr(void* x, void* r, const void* p, const void* Ap, const double* sc, int dtype, int64_t n,
                   hipStream_t s);
 int launch_pcg_p(void* p, const void* z, const double* sc, int dtype, int64_t n, hipStream_t s);

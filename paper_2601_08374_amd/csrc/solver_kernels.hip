@@ -253,6 +253,44 @@ __global__ void splitmix_kernel(T* __restrict__ v, uint64_t seed, int64_t n) {
     }
 }
 
+// One power-iteration pass after w = A v, in one read of v, w and dinv: z = dinv w is
+// written out and three stage-1 sums are formed, v.w -> part[blk], v.Dv (v_i^2 / dinv_i)
+// -> part[nb + blk], z.z -> part[2 nb + blk] (part[3 nb + blk] = 0).  The per-element
+// arithmetic and the block reductions are those of the separate dot, vdv and scaling
+// kernels, so the sums are the same.
+template <typename T>
+__global__ void power_pass_kernel(const T* __restrict__ v, const T* __restrict__ w, const T* __restrict__ dinv,
+                                  T* __restrict__ z, int64_t n, double* __restrict__ part) {
+    __shared__ double s0[kBlock], s1[kBlock], s2[kBlock];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    GRID_STRIDE(i, n) {
+        const double vv = (double)v[i];
+        const T zt = dinv[i] * w[i];
+        z[i] = zt;
+        a0 += vv * (double)w[i];
+        a1 += vv * vv / (double)dinv[i];
+        a2 += (double)zt * (double)zt;
+    }
+    s0[threadIdx.x] = a0;
+    s1[threadIdx.x] = a1;
+    s2[threadIdx.x] = a2;
+    __syncthreads();
+    for (int k = kBlock / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) {
+            s0[threadIdx.x] += s0[threadIdx.x + k];
+            s1[threadIdx.x] += s1[threadIdx.x + k];
+            s2[threadIdx.x] += s2[threadIdx.x + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = s0[0];
+        part[gridDim.x + blockIdx.x] = s1[0];
+        part[2 * gridDim.x + blockIdx.x] = s2[0];
+        part[3 * gridDim.x + blockIdx.x] = 0.0;
+    }
+}
+
 // Weighted dot sum v_i^2 / dinv_i (= v.Dv) into part (stage 1)
 template <typename T>
 __global__ void vdv_partial_kernel(const T* __restrict__ v, const T* __restrict__ dinv, int64_t n,
@@ -799,6 +837,18 @@ int launch_dot_final(const double* part, double* scal, int op, int slot, hipStre
 
 int launch_pcg_init(const double* part, double* scal, double rtol, int stop, hipStream_t s) {
     hipLaunchKernelGGL(pcg_init_scalars_kernel, dim3(1), dim3(kBlock), 0, s, part, kReduceBlocks, scal, rtol, stop);
+    PA_CHECK_LAUNCH();
+    return PA_OK;
+}
+
+int launch_power_pass(const void* v, const void* w, const void* dinv, void* z, int dtype, int64_t n, double* part,
+                      hipStream_t s) {
+    if (dtype == PA_F64)
+        hipLaunchKernelGGL(power_pass_kernel<double>, dim3(kReduceBlocks), dim3(kBlock), 0, s, cp<double>(v),
+                           cp<double>(w), cp<double>(dinv), mp<double>(z), n, part);
+    else
+        hipLaunchKernelGGL(power_pass_kernel<float>, dim3(kReduceBlocks), dim3(kBlock), 0, s, cp<float>(v),
+                           cp<float>(w), cp<float>(dinv), mp<float>(z), n, part);
     PA_CHECK_LAUNCH();
     return PA_OK;
 }
