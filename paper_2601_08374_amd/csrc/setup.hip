@@ -2,6 +2,10 @@
 // the operator diagonal and the load vector.
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "internal.h"
 #include "kernels.h"
 
@@ -107,10 +111,34 @@ __global__ void tables_kernel(int p, int q, double* out) {
 
 int tables_words(int p, int q) { return 2 * (p + 1) * q + 2 * q + 5 * (p + 1); }
 
+// The tables depend on (p, q) only: the first operator of a (p, q) computes them on the
+// device, later ones (solver levels, served requests) copy the kept words.
+struct TableWords {
+    Tables host;
+    std::vector<double> words;
+};
+static std::mutex g_tables_mu;
+static std::map<std::pair<int, int>, TableWords> g_tables;
+
 int compute_tables(int p, int q, hipStream_t s, double** d_tab, Tables* host) {
     const int n = tables_words(p, q);
     double* d = nullptr;
     PA_HIP(hipMalloc(&d, n * sizeof(double)));
+    {
+        std::lock_guard<std::mutex> lk(g_tables_mu);
+        const auto it = g_tables.find({p, q});
+        if (it != g_tables.end()) {
+            const hipError_t e = hipMemcpyAsync(d, it->second.words.data(), n * sizeof(double),
+                                                hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) {
+                (void)hipFree(d);
+                return fail(PA_EHIP, "1D table upload failed: %s", hipGetErrorString(e));
+            }
+            *host = it->second.host;
+            *d_tab = d;
+            return PA_OK;
+        }
+    }
     hipLaunchKernelGGL(tables_kernel, dim3(1), dim3(64), 0, s, p, q, d);
     hipError_t e = hipGetLastError();
     std::vector<double> h(n);
@@ -130,6 +158,10 @@ int compute_tables(int p, int q, hipStream_t s, double** d_tab, Tables* host) {
         host->G[i] = h[D + 2 * Q + D * Q + i];
     }
     *d_tab = d;
+    {
+        std::lock_guard<std::mutex> lk(g_tables_mu);
+        g_tables.emplace(std::make_pair(p, q), TableWords{*host, std::move(h)});
+    }
     return PA_OK;
 }
 
