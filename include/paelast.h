@@ -101,7 +101,7 @@ typedef struct pa_solve_opts_t {
     int h_levels;             /* number of h-coarsenings at p = 1 (-1: automatic)              */
     int cheb_degree;          /* Chebyshev degree k (Sec. 3.1 uses 2)                          */
     int power_iters;          /* power iterations for lambda_max (Sec. 3.1 uses 10)            */
-    double cheb_lo_frac;      /* smoothing interval [lo_frac*lmax, lmax]                       */
+    double cheb_lo_frac;      /* smoothing interval [lo_frac*lmax, lmax] (default 0.1)         */
     double cheb_safety;       /* lmax = safety * estimate                                      */
     int max_iter;             /* outer PCG iteration cap (Sec. 3.2: 5000)                      */
     double inner_rtol;        /* PA_SOLVE_F32_IR: inner FP32 PCG tolerance (default 3e-3)      */

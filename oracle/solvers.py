@@ -60,7 +60,7 @@ def power_iteration(A: np.ndarray, d: np.ndarray, v0: np.ndarray, iters: int = 1
     return lam
 
 
-def chebyshev_interval(lam_hat: float, lo_frac: float = 0.3, safety: float = 1.2):
+def chebyshev_interval(lam_hat: float, lo_frac: float = 0.1, safety: float = 1.2):
     lmax = safety * lam_hat
     return lo_frac * lmax, lmax
 

@@ -297,7 +297,9 @@ void pa_solve_opts_default(pa_solve_opts_t* o) {
     o->h_levels = -1;
     o->cheb_degree = 2;
     o->power_iters = 10;
-    o->cheb_lo_frac = 0.3;
+    // [0.1, 1] x 1.2 lambda_hat: measured 23-29% faster GMG-PCG solves at p >= 4 than [0.3, 1]
+    // (fewer iterations); narrower safety margins diverged on some boxes
+    o->cheb_lo_frac = 0.1;
     o->cheb_safety = 1.2;
     o->max_iter = 5000;
     // each refinement step gains only 2-3 digits (the FP32 operator's own error bounds the

@@ -114,5 +114,5 @@ def test_solve_opts_defaults():
     o = capi.pa_solve_opts_t()
     lib.pa_solve_opts_default(C.byref(o))
     assert o.cheb_degree == 2 and o.power_iters == 10 and o.max_iter == 5000
-    assert abs(o.cheb_lo_frac - 0.3) < 1e-15 and abs(o.cheb_safety - 1.2) < 1e-15
+    assert abs(o.cheb_lo_frac - 0.1) < 1e-15 and abs(o.cheb_safety - 1.2) < 1e-15
     assert abs(o.inner_rtol - 3e-3) < 1e-18 and o.inner_max_iter == 50 and o.max_outer == 20
