@@ -482,16 +482,16 @@ int setup_gmg(pa_op* op, const pa_solve_opts_t* o, pa_gmg** out) {
             Level& c = G->L.back();
             G->Nc = (int)c.N;
             double* A = nullptr;
-            double* col = nullptr;
+            double* work = nullptr;
             if (hipMalloc(&A, (size_t)G->Nc * G->Nc * sizeof(double)) != hipSuccess ||
-                hipMalloc(&col, (size_t)coarse_invert_words(G->Nc) * sizeof(double)) != hipSuccess) {
+                hipMalloc(&work, (size_t)coarse_invert_words(G->Nc) * sizeof(double)) != hipSuccess) {
                 (void)hipGetLastError();
                 if (A) (void)hipFree(A);
                 rc = fail(PA_ENOMEM, "coarse matrix allocation failed (%d dofs)", G->Nc);
                 break;
             }
             rc = launch_coarse_assemble(A, G->Nc, c.op, G->stream);
-            if (!rc) rc = coarse_invert(A, col, G->Nc, G->stream);
+            if (!rc) rc = coarse_invert(A, work, G->Nc, G->stream);
             if (!rc && G->vdtype == PA_F32) {
                 void* a32 = nullptr;
                 rc = alloc_vec(&a32, (int64_t)G->Nc * G->Nc, PA_F32);
@@ -503,7 +503,7 @@ int setup_gmg(pa_op* op, const pa_solve_opts_t* o, pa_gmg** out) {
                 }
             }
             PA_HIP(hipStreamSynchronize(G->stream));
-            (void)hipFree(col);
+            (void)hipFree(work);
             G->cinv = A;
             if (rc) break;
         }

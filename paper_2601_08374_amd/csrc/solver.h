@@ -34,7 +34,6 @@ struct HAxis {
 int launch_dot(const void* a, const void* b, const void* c, int dtype, int64_t n, double* part, hipStream_t s);
 int launch_dot_final(const double* part, double* scal, int op, int slot, hipStream_t s);
 int launch_pcg_init(const double* part, double* scal, double rtol, int stop, hipStream_t s);
-int launch_vdv(const void* v, const void* dinv, int dtype, int64_t n, double* part, hipStream_t s);
 // Power-iteration pass: z = dinv w and the stage-1 sums of v.w, v.Dv (part, part + nb) and z.z
 // (part + 2 nb, with zeros at part + 3 nb); part holds 4 kReduceBlocks doubles.
 int launch_power_pass(const void* v, const void* w, const void* dinv, void* z, int dtype, int64_t n, double* part,
@@ -42,7 +41,6 @@ int launch_power_pass(const void* v, const void* w, const void* dinv, void* z, i
 int launch_pcg_xr(void* x, void* r, const void* p, const void* Ap, const double* sc, int dtype, int64_t n,
                   hipStream_t s);
 int launch_pcg_p(void* p, const void* z, const double* sc, int dtype, int64_t n, hipStream_t s);
-int launch_axpby(void* y, const void* x, double a, double b, int dtype, int64_t n, hipStream_t s);
 int launch_residual(void* r, const void* b, const void* Ax, int dtype, int64_t n, hipStream_t s);
 int launch_copy(void* y, const void* x, int dtype, int64_t n, hipStream_t s);
 int launch_cast_scale(void* y, int dty, const void* x, int dtx, const double* sc, int slot, int inv_sqrt, int64_t n,
@@ -52,7 +50,6 @@ int launch_cheb_step(void* x, void* r, const void* t, void* d, const void* dinv,
                      bool last, int dtype, int64_t n, hipStream_t s);
 int launch_cheb_start(void* r, void* d, const void* dinv, const void* b, const void* t, double c, int dtype,
                       int64_t n, hipStream_t s);
-int launch_cheb_first(void* d, const void* dinv, const void* r, double c, int dtype, int64_t n, hipStream_t s);
 int launch_add(void* y, const void* x, int dtype, int64_t n, hipStream_t s);
 int launch_reciprocal(void* y, int dtype, int64_t n, hipStream_t s);
 int launch_splitmix(void* v, int dtype, uint64_t seed, int64_t n, hipStream_t s);

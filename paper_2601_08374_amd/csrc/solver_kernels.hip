@@ -156,13 +156,6 @@ __global__ void pcg_p_kernel(T* __restrict__ p, const T* __restrict__ z, const d
 
 // ---------------------------------------------------------------- generic vector ops
 template <typename T>
-__global__ void axpby_kernel(T* __restrict__ y, const T* __restrict__ x, double a, double b, int64_t n) {
-    // y = a*x + b*y
-    const T ta = (T)a, tb = (T)b;
-    GRID_STRIDE(i, n) y[i] = ta * x[i] + tb * y[i];
-}
-
-template <typename T>
 __global__ void residual_kernel(T* __restrict__ r, const T* __restrict__ b, const T* __restrict__ Ax, int64_t n) {
     GRID_STRIDE(i, n) r[i] = b[i] - Ax[i];
 }
@@ -223,14 +216,6 @@ __global__ void cheb_start_kernel(T* __restrict__ r, T* __restrict__ d, const T*
     }
 }
 
-// d = c * dinv * r ; optionally x = d (x_set) or x += d (x_add)
-template <typename T>
-__global__ void cheb_first_kernel(T* __restrict__ d, const T* __restrict__ dinv, const T* __restrict__ r, double c,
-                                  int64_t n) {
-    const T tc = (T)c;
-    GRID_STRIDE(i, n) d[i] = tc * dinv[i] * r[i];
-}
-
 template <typename T>
 __global__ void add_kernel(T* __restrict__ y, const T* __restrict__ x, int64_t n) {
     GRID_STRIDE(i, n) y[i] += x[i];
@@ -255,9 +240,8 @@ __global__ void splitmix_kernel(T* __restrict__ v, uint64_t seed, int64_t n) {
 
 // One power-iteration pass after w = A v, in one read of v, w and dinv: z = dinv w is
 // written out and three stage-1 sums are formed, v.w -> part[blk], v.Dv (v_i^2 / dinv_i)
-// -> part[nb + blk], z.z -> part[2 nb + blk] (part[3 nb + blk] = 0).  The per-element
-// arithmetic and the block reductions are those of the separate dot, vdv and scaling
-// kernels, so the sums are the same.
+// -> part[nb + blk], z.z -> part[2 nb + blk] (part[3 nb + blk] = 0).  Each sum is the
+// fixed-grid, fixed-order block reduction of the dot kernels, so it is deterministic.
 template <typename T>
 __global__ void power_pass_kernel(const T* __restrict__ v, const T* __restrict__ w, const T* __restrict__ dinv,
                                   T* __restrict__ z, int64_t n, double* __restrict__ part) {
@@ -288,28 +272,6 @@ __global__ void power_pass_kernel(const T* __restrict__ v, const T* __restrict__
         part[gridDim.x + blockIdx.x] = s1[0];
         part[2 * gridDim.x + blockIdx.x] = s2[0];
         part[3 * gridDim.x + blockIdx.x] = 0.0;
-    }
-}
-
-// Weighted dot sum v_i^2 / dinv_i (= v.Dv) into part (stage 1)
-template <typename T>
-__global__ void vdv_partial_kernel(const T* __restrict__ v, const T* __restrict__ dinv, int64_t n,
-                                   double* __restrict__ part) {
-    __shared__ double s0[kBlock];
-    double acc = 0.0;
-    GRID_STRIDE(i, n) {
-        const double a = (double)v[i];
-        acc += a * a / (double)dinv[i];
-    }
-    s0[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) s0[threadIdx.x] += s0[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = s0[0];
-        part[gridDim.x + blockIdx.x] = 0.0;
     }
 }
 
@@ -853,17 +815,6 @@ int launch_power_pass(const void* v, const void* w, const void* dinv, void* z, i
     return PA_OK;
 }
 
-int launch_vdv(const void* v, const void* dinv, int dtype, int64_t n, double* part, hipStream_t s) {
-    if (dtype == PA_F64)
-        hipLaunchKernelGGL(vdv_partial_kernel<double>, dim3(kReduceBlocks), dim3(kBlock), 0, s, cp<double>(v),
-                           cp<double>(dinv), n, part);
-    else
-        hipLaunchKernelGGL(vdv_partial_kernel<float>, dim3(kReduceBlocks), dim3(kBlock), 0, s, cp<float>(v),
-                           cp<float>(dinv), n, part);
-    PA_CHECK_LAUNCH();
-    return PA_OK;
-}
-
 int launch_pcg_xr(void* x, void* r, const void* p, const void* Ap, const double* sc, int dtype, int64_t n,
                   hipStream_t s) {
     if (dtype == PA_F64)
@@ -883,17 +834,6 @@ int launch_pcg_p(void* p, const void* z, const double* sc, int dtype, int64_t n,
     else
         hipLaunchKernelGGL(pcg_p_kernel<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<float>(p), cp<float>(z), sc,
                            n);
-    PA_CHECK_LAUNCH();
-    return PA_OK;
-}
-
-int launch_axpby(void* y, const void* x, double a, double b, int dtype, int64_t n, hipStream_t s) {
-    if (dtype == PA_F64)
-        hipLaunchKernelGGL(axpby_kernel<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<double>(y), cp<double>(x),
-                           a, b, n);
-    else
-        hipLaunchKernelGGL(axpby_kernel<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<float>(y), cp<float>(x), a,
-                           b, n);
     PA_CHECK_LAUNCH();
     return PA_OK;
 }
@@ -978,17 +918,6 @@ int launch_cheb_start(void* r, void* d, const void* dinv, const void* b, const v
     else
         hipLaunchKernelGGL(cheb_start_kernel<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<float>(r),
                            mp<float>(d), cp<float>(dinv), cp<float>(b), cp<float>(t), c, n);
-    PA_CHECK_LAUNCH();
-    return PA_OK;
-}
-
-int launch_cheb_first(void* d, const void* dinv, const void* r, double c, int dtype, int64_t n, hipStream_t s) {
-    if (dtype == PA_F64)
-        hipLaunchKernelGGL(cheb_first_kernel<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<double>(d),
-                           cp<double>(dinv), cp<double>(r), c, n);
-    else
-        hipLaunchKernelGGL(cheb_first_kernel<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, mp<float>(d),
-                           cp<float>(dinv), cp<float>(r), c, n);
     PA_CHECK_LAUNCH();
     return PA_OK;
 }
