@@ -40,10 +40,10 @@ STEP_PS = (1, 2, 4, 6, 8)
 # source hash of the kernels they were taken on, so an edited kernel reports
 # null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("aeac958800f6e808", 1, "f64"): 335806726,
-    ("aeac958800f6e808", 2, "f64"): 337590787,
-    ("aeac958800f6e808", 4, "f64"): 225746467,
-    ("aeac958800f6e808", 8, "f64"): 158617757,
+    ("91dfd15286cfdee0", 1, "f64"): 335789264,
+    ("91dfd15286cfdee0", 2, "f64"): 316189840,
+    ("91dfd15286cfdee0", 4, "f64"): 197893779,
+    ("91dfd15286cfdee0", 8, "f64"): 138062614,
 }
 
 

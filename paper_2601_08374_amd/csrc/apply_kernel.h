@@ -844,7 +844,9 @@ __global__ void __launch_bounds__(256)
 pa_skeleton_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ sk, const Geom g,
                    const SkelNodes sn, const int add) {
     using SK = Skel<P + 1>;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    // each XCD takes a contiguous range of nodes, as the apply kernel gave it a contiguous
+    // range of elements: most of a node's contributions were written through the same L2
+    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (t >= sn.total) return;
     int gx, gy, gz;
     skel_node_coords<P>(t, sn, g, gx, gy, gz);
