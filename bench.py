@@ -11,10 +11,13 @@ two materials per element (E = 1 and 100, nu = 0.3, seed 1), x ~ U[-1,1]
 different buffer pair from a rotating set of >= 1 GB so that x and y stream
 from HBM rather than the 256 MB last-level cache.
 
-Printed: one JSON line with value = aggregate FP64 apply throughput over the
-step (total dofs / wall time, GDoF/s), the per-p FP64/FP32 sweep for p = 1..8,
-the roofline of the dominant kernel (HIP-event timing of its launches inside
-the timed region) and the FP64 CPU oracle timed on a bounded sample.
+Printed: one short JSON line (the last line of stdout) with value = aggregate
+FP64 apply throughput over the step (total dofs / wall time, GDoF/s), the
+roofline of the dominant kernel (HIP-event timing of its launches inside the
+timed region), the FP64 CPU oracle timed on a bounded sample, the per-p
+FP64/FP32 apply sweep for p = 1..8 and brief solve and serving figures.  The
+full results (sweep rates, ablation, material/geometry/unstructured forms,
+solves, serving) go to the --detail file.
 """
 from __future__ import annotations
 
@@ -48,7 +51,7 @@ MEASURED_TRAFFIC = {
 
 
 def log(msg: str):
-    """Progress line on stderr (the JSON result is the only stdout line)."""
+    """Progress line on stderr (the summary JSON is the last stdout line)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
@@ -74,37 +77,80 @@ def apply_kernel_names(p: int) -> str:
     return f"pa_apply_kernel<P={p},Q={p + 2},double> + pa_skeleton_kernel<P={p},double>"
 
 
-def cpu_baseline(ps, budget_s: float = 25.0):
-    """Time the FP64 oracle (element-matrix GEMM apply) on the host cores."""
+def cpu_model() -> str:
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(ps, reps: int = 3):
+    """Time the FP64 oracle apply (element-matrix GEMM + scatter) on the host cores.
+
+    Sample: the first 1/8 of the sheared box of each p (n // 2 elements per axis, same
+    element size, two materials, x ~ U[-1,1]).  Per p: element-matrix formation timed
+    once, then one warm-up apply and the median of `reps` applies with the default thread
+    pools, then the median of `reps` applies with every thread pool limited to one thread.
+    `cores` is the number of threads the timed applies kept busy (process CPU time over
+    wall time), `host_cores` the cores the process may run on."""
     import numpy as np
     import synthetic as syn
     from oracle import elasticity
+    from threadpoolctl import threadpool_limits
 
-    cores = len(os.sched_getaffinity(0))
+    host_cores = len(os.sched_getaffinity(0))
     res = {}
-    tot_dofs, tot_t = 0, 0.0
-    t_start = time.perf_counter()
+    tot_dofs = tot_t = tot_t1 = 0.0
+    cpu_s = wall_s = 0.0
     for p in ps:
-        if time.perf_counter() - t_start > budget_s:
-            break
-        mesh = syn.sheared_box_mesh(p)
-        lam, mu = syn.two_material_lame(mesh.num_elements, seed=1)
+        sub = _sub_box(syn.sheared_box_mesh(p), 2)
+        lam, mu = syn.two_material_lame(sub.num_elements, seed=1)
         t0 = time.perf_counter()
-        op = elasticity.Operator(mesh, p, p + 2, lam, mu)
+        op = elasticity.Operator(sub, p, p + 2, lam, mu)
         t_setup = time.perf_counter() - t0
         x = syn.uniform_vector(op.N, 0)
-        t0 = time.perf_counter()
-        op.apply(x)
-        t = time.perf_counter() - t0
-        res[p] = {"gdofs": op.N / t / 1e9, "t_apply_s": t, "t_setup_s": t_setup, "N": op.N}
+        op.apply(x)                                   # warm-up
+        ts = []
+        for _ in range(reps):
+            c0, t0 = time.process_time(), time.perf_counter()
+            op.apply(x)
+            ts.append(time.perf_counter() - t0)
+            cpu_s += time.process_time() - c0
+            wall_s += ts[-1]
+        t = float(np.median(ts))
+        with threadpool_limits(limits=1):
+            t1s = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                op.apply(x)
+                t1s.append(time.perf_counter() - t0)
+        t1 = float(np.median(t1s))
+        res[p] = {"gdofs": op.N / t / 1e9, "gdofs_1thread": op.N / t1 / 1e9, "t_apply_s": t,
+                  "t_apply_1thread_s": t1, "t_setup_s": t_setup, "N": op.N, "n": list(sub.n)}
         tot_dofs += op.N
         tot_t += t
+        tot_t1 += t1
         del op
-    return {"value": tot_dofs / tot_t / 1e9 if tot_t else None, "unit": "GDoF/s", "cores": cores,
-            "kind": "oracle",
-            "sample": "one FP64 oracle apply (batched element-matrix GEMM + scatter) of the sheared-box "
-                      f"operator at each p in {sorted(res)} (full size, ~4.2M dofs each); element-matrix "
-                      "formation timed separately (t_setup_s)",
+    return {"value": tot_dofs / tot_t / 1e9, "unit": "GDoF/s", "cores": max(1, round(cpu_s / wall_s)),
+            "host_cores": host_cores, "cpu_model": cpu_model(), "kind": "oracle",
+            "value_1thread": tot_dofs / tot_t1 / 1e9,
+            "sample": "FP64 oracle apply (batched element-matrix GEMM + scatter) on the first 1/8 of the "
+                      f"sheared box at each p in {list(ps)} (n//2 elements per axis, ~0.5M dofs each); one "
+                      f"warm-up, median of {reps}; also with thread pools limited to 1; element-matrix "
+                      "formation timed separately",
             "per_p": res}
 
 
@@ -202,6 +248,53 @@ def measured_ceilings(torch, dev, reps: int = 5):
     return out
 
 
+def _r(v, nd=3):
+    return None if v is None else round(float(v), nd)
+
+
+def _sig(v, n=3):
+    """v to n significant digits."""
+    return None if v is None else float(f"{float(v):.{n}g}")
+
+
+def compact_summary(res: dict) -> dict:
+    """The one-line result (well under 2 KB): the contract fields, the roofline of the
+    dominant kernel, the CPU baseline, and per-p FP64/FP32 apply GDoF/s; solve and serving
+    figures in brief.  Everything else stays in the detail file."""
+    keys = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+            "scaling", "vs_baseline", "dtype", "data")
+    out = {k: res[k] for k in keys if k in res}
+    cfg = res["config"]
+    out["config"] = {"workload": cfg["workload"][:180], "parallelism": cfg["parallelism"],
+                     "dofs": {str(p): n for p, n in cfg["dofs"].items()}}
+    rf = res["roofline"]
+    out["roofline"] = {k: rf[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel",
+                                          "flops_per_launch", "algorithmic_bytes_per_launch", "launch_us",
+                                          "measured_peak", "frac_measured") if k in rf}
+    out["step_per_p_gdofs"] = {str(p): _r(v, 1) for p, v in res["step_per_p_gdofs"].items()}
+    cb = res.get("cpu_baseline")
+    if cb:
+        out["cpu_baseline"] = {"value": _sig(cb["value"]), "unit": cb["unit"], "cores": cb["cores"],
+                               "host_cores": cb["host_cores"], "cpu_model": cb["cpu_model"].strip()[:48],
+                               "kind": cb["kind"], "value_1thread": _sig(cb["value_1thread"]),
+                               "sample": "FP64 oracle apply, first 1/8 of the sheared box at each step p, "
+                                         "warm-up + median of 3",
+                               "per_p": {str(p): _sig(v["gdofs"]) for p, v in cb["per_p"].items()}}
+    sw = res.get("sweep")
+    if sw:
+        out["sweep_gdofs"] = {d: {str(p): _r(sw[p][d]["gdofs"], 1) for p in sw} for d in ("f64", "f32")}
+        out["sweep_frac_alu_f64"] = {str(p): _r(sw[p]["f64"]["frac_alu_peak"], 3) for p in sw}
+    sv = res.get("solve")
+    if sv:
+        out["solve_ms"] = {k[1:]: {m: _r(v[m]["solve_s"] * 1e3, 1) for m in ("f64", "f32_prec", "f32_ir") if m in v}
+                           for k, v in sv.items() if k.startswith("p") and k[1:].isdigit()}
+    se = res.get("serve")
+    if se:
+        out["serve"] = {m: {"solves_per_s": _r(se[m]["solves_per_s"], 2), "p50_s": _r(se[m]["p50_latency_s"], 3),
+                            "p99_s": _r(se[m]["p99_latency_s"], 3)} for m in ("f64", "f32_ir", "f32_prec") if m in se}
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,6 +322,8 @@ def main(argv=None):
     ap.add_argument("--solve-mode", choices=("f64", "f32_ir", "f32_prec"), default="f64")
     ap.add_argument("--dtype", choices=("f64", "f32"), default="f64")
     ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="file for the full results (the stdout line is a summary); empty: none")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -375,9 +470,9 @@ def main(argv=None):
         "value": round(value, 4), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(wall / args.steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "operator-apply sweep, globally sheared box (shear 0.2), ~4.2M dofs, "
-                               "p in {1,2,4,6,8}, q=p+2, two materials (E=1,100; nu=0.3; seed 1), "
-                               "x~U[-1,1] seed 0, cold rotating buffers",
+        "config": {"workload": "FP64 apply at p=1,2,4,6,8 on the sheared box (shear 0.2), (120/p,120/p,96/p) "
+                               "elements, ~4.2M dofs, q=p+2, E in {1,100} nu=0.3 seed 1, x~U[-1,1] seed 0, "
+                               "cold buffers",
                    "dofs": {p: setups[p]["N"] for p in STEP_PS}, "parallelism": "single GPU"},
         "step_per_p_gdofs": {p: round(setups[p]["N"] / (per_p_ms[p] * 1e-3) / 1e9, 3) for p in STEP_PS},
         "roofline": roofline,
@@ -460,7 +555,17 @@ def main(argv=None):
             if section in result:
                 log(f"cpu baseline (oracle), {section}")
                 result[section]["cpu_oracle"] = cpu_baseline_forms(section)
-    print(json.dumps(result), flush=True)
+    detail = args.detail
+    if detail:
+        try:
+            os.makedirs(os.path.dirname(os.path.abspath(detail)), exist_ok=True)
+            with open(detail, "w") as fh:
+                json.dump(result, fh, indent=1)
+            log(f"full results written to {detail}")
+        except OSError as exc:
+            log(f"could not write {detail}: {exc}")
+    line = json.dumps(compact_summary(result), separators=(",", ":"))
+    print(line, flush=True)
     return 0
 
 

@@ -124,8 +124,8 @@ typedef struct pa_solve_info_t {
 } pa_solve_info_t;
 
 /* Fill *o with the defaults: F64, PA_STOP_PREC, full p-hierarchy, automatic h,
- * k = 2, 10 power iterations, interval [0.3, 1] * 1.2 * estimate, 5000 iterations,
- * inner rtol 1e-4 / 50 iterations, 20 refinement steps, seed 7, coarse <= 3000 dofs. */
+ * k = 2, 10 power iterations, interval [0.1, 1] * 1.2 * estimate, 5000 iterations,
+ * inner rtol 3e-3 / 50 iterations, 20 refinement steps, seed 7, coarse <= 3000 dofs. */
 void pa_solve_opts_default(pa_solve_opts_t* o);
 
 /* ---- operator --------------------------------------------------------------- */

@@ -98,7 +98,7 @@ EXTRA_POINT_FLOPS = {"qpoint_iso": 2, "anisotropic": 60, "trilinear": 46}
 
 
 def flops_per_element(p: int, q: int | None = None) -> int:
-    """Per-element FLOPs of the optimized operator, the paper's count (Sec. 5.3.1 table):
+    """Per-element FLOPs of the optimized operator, the paper's count (Sec. 5.4.1 table):
     30 D^3 Q + 36 D^2 Q^2 + 36 D Q^3 + 113 Q^3 + 12 D^3, D = p+1, Q = p+2."""
     D = p + 1
     Q = p + 2 if q is None else q
