@@ -15,8 +15,11 @@ definitions, sharing no code with the GPU path:
 * ``elasticity``  -- element stiffness matrices by direct quadrature of the weak
                      form (eqs. 3-4) over full 3D basis functions (no sum
                      factorization), the global apply y = sum_e G_e^T K_e G_e x,
-                     load vectors, the constrained operator.
-* ``solvers``     -- direct solves, the diagonal, power iteration, Chebyshev
+                     load vectors, the constrained operator, and the sum of
+                     element magnitudes sum_e G_e^T |K_e| G_e x that scales the
+                     rounding of an evaluation of A x.
+* ``solvers``     -- direct solves (dense, and block Cholesky over x-slabs for
+                     cantilevers of ~1e5 dofs), power iteration, Chebyshev
                      smoothing, p/h prolongation matrices, a dense V-cycle and
                      PCG (Sec. 3), used as references on small problems.
 

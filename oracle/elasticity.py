@@ -128,6 +128,29 @@ class Operator:
             Y[self.ess] = (x if multi else x[:, None])[self.ess]
         return Y if multi else Y[:, 0]
 
+    def abs_apply(self, x, constrained: bool = False) -> np.ndarray:
+        """sum_e G_e^T |K^e| G_e x, with |K^e| the entrywise absolute values of each element
+        matrix: for x >= 0 this is the sum of the magnitudes of the element products that an
+        evaluation of A x adds up, the scale of its rounding error.  The constrained form
+        has 0 on the clamped columns and x on the clamped rows (identity rows and columns)."""
+        x_in = np.asarray(x, dtype=np.float64)
+        x = x_in
+        if constrained:
+            x = x_in.copy()
+            x[self.ess] = 0.0
+        y = np.zeros(self.N)
+        for els, Kl, Km in self.groups:
+            # elements with the same (lambda, mu) in a group share |K^e|
+            pairs = np.stack([self.lam[els], self.mu[els]], axis=1)
+            uniq, inv = np.unique(pairs, axis=0, return_inverse=True)
+            for k, (lv, mv) in enumerate(uniq):
+                d = self.edofs[els[inv.ravel() == k]]
+                ye = np.einsum("ij,ej->ei", np.abs(lv * Kl + mv * Km), x[d])
+                y += np.bincount(d.ravel(), ye.ravel(), minlength=self.N)
+        if constrained:
+            y[self.ess] = x_in[self.ess]
+        return y
+
     def dense(self, constrained: bool = False) -> np.ndarray:
         """Assembled dense matrix (small problems only)."""
         A = np.zeros((self.N, self.N))

@@ -1,6 +1,7 @@
 """Reference solvers and multigrid components (dense FP64, small problems).
 
-* Direct solves of the constrained system A U = F (eq. 5).
+* Direct solves of the constrained system A U = F (eq. 5): dense, and a block
+  Cholesky over the element slabs of a box along x (block tridiagonal there).
 * Power iteration for lambda_max(D^{-1} A) and Chebyshev-Jacobi smoothing
   (Sec. 3.1: a Chebyshev polynomial in D^{-1} A applied to the residual,
   lambda_max from 10 power iterations).  The Chebyshev recurrence is the
@@ -166,3 +167,96 @@ def pcg(A, b, prec, rtol: float, max_iter: int = 1000, stop: str = "prec"):
         p = z + (rz_new / rz) * p
         rz = rz_new
     return x, it
+
+
+class SlabCholesky:
+    """Direct solve of the constrained system A_c U = F (eq. 5) of a box operator
+    (oracle.elasticity.Operator) by block Cholesky over the element slabs along x.
+
+    The dofs are grouped by node plane gx: block s holds the planes s p + 1 .. (s+1) p,
+    block 0 also plane 0.  An element of slab s couples only the planes s p .. (s+1) p,
+    so the assembled matrix is block tridiagonal in these blocks, and block s meets block
+    s-1 only through the interface plane s p (the last plane of block s-1).  Elimination:
+    S_0 = A_00 and S_s = A_ss - A_{s,s-1} S_{s-1}^{-1} A_{s-1,s}, each factored by dense
+    Cholesky (a library routine); a solve is the forward and back substitution.  The
+    blocks are assembled from the oracle's element matrices; clamped dofs get identity
+    rows and columns.  Memory: one dense block of 3 p (n1 p + 1)(n2 p + 1) dofs per slab.
+    """
+
+    def __init__(self, op):
+        from scipy.linalg import cho_factor
+        mesh, p = op.mesh, op.p
+        Nx, Ny, Nz = omesh.grid_shape(mesh, p)
+        Nn = Nx * Ny * Nz
+        nx = mesh.n[0]
+        dof = np.arange(3 * Nn)
+        gx = (dof % Nn) % Nx
+        blk = np.maximum(gx - 1, 0) // p                      # plane -> block (planes 0..p: block 0)
+        order = np.lexsort((dof, blk))                        # dofs grouped by block, ascending
+        loc = np.empty(3 * Nn, dtype=np.int64)
+        sizes = np.bincount(blk, minlength=nx)
+        starts = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+        loc[order] = np.arange(3 * Nn) - np.repeat(starts, sizes)
+        self.nblk, self.blk, self.loc = nx, blk, loc
+        self.members = [order[starts[s]:starts[s] + sizes[s]] for s in range(nx)]
+        # interface of block s with block s+1: its dofs on plane (s+1) p, in local order
+        self.iface = [np.sort(loc[self.members[s][gx[self.members[s]] == (s + 1) * p]]) for s in range(nx)]
+        ipos = [np.full(sizes[s], -1, dtype=np.int64) for s in range(nx)]
+        for s in range(nx):
+            ipos[s][self.iface[s]] = np.arange(len(self.iface[s]))
+        Ad = [np.zeros((sizes[s], sizes[s])) for s in range(nx)]
+        Ao = [None] + [np.zeros((sizes[s], len(self.iface[s - 1]))) for s in range(1, nx)]
+        ex = np.arange(mesh.num_elements) % nx
+        for e in range(mesh.num_elements):
+            K = op.element_matrix(e)
+            d = op.edofs[e]
+            s = ex[e]
+            own = blk[d] == s
+            io, ip = np.nonzero(own)[0], np.nonzero(~own)[0]
+            lo, lp = loc[d[io]], loc[d[ip]]
+            Ad[s][np.ix_(lo, lo)] += K[np.ix_(io, io)]
+            if len(ip):
+                Ad[s - 1][np.ix_(lp, lp)] += K[np.ix_(ip, ip)]
+                Ao[s][np.ix_(lo, ipos[s - 1][lp])] += K[np.ix_(io, ip)]
+        ess = op.ess
+        for s in range(nx):
+            m = ess[self.members[s]]
+            Ad[s][m, :] = 0.0
+            Ad[s][:, m] = 0.0
+            Ad[s][m, m] = 1.0
+            if s > 0:
+                Ao[s][m, :] = 0.0
+                Ao[s][:, ess[self.members[s - 1]][self.iface[s - 1]]] = 0.0
+        self.Ao = Ao
+        self.F = []
+        for s in range(nx):
+            S = Ad[s]
+            if s > 0:
+                I = self.iface[s - 1]
+                E = np.zeros((len(self.members[s - 1]), len(I)))
+                E[I, np.arange(len(I))] = 1.0
+                Z = self._solve_block(s - 1, E)[I]             # (S_{s-1}^{-1})_{II}
+                S = S - Ao[s] @ Z @ Ao[s].T
+            self.F.append(cho_factor(S, lower=True))
+            Ad[s] = None
+
+    def _solve_block(self, s, B):
+        from scipy.linalg import cho_solve
+        return cho_solve(self.F[s], B)
+
+    def solve(self, b) -> np.ndarray:
+        b = np.asarray(b, dtype=np.float64)
+        nx = self.nblk
+        y = [b[self.members[s]].copy() for s in range(nx)]
+        for s in range(1, nx):
+            y[s] -= self.Ao[s] @ self._solve_block(s - 1, y[s - 1])[self.iface[s - 1]]
+        x = [None] * nx
+        x[nx - 1] = self._solve_block(nx - 1, y[nx - 1])
+        for s in range(nx - 2, -1, -1):
+            t = y[s].copy()
+            t[self.iface[s]] -= self.Ao[s + 1].T @ x[s + 1]
+            x[s] = self._solve_block(s, t)
+        out = np.empty_like(b)
+        for s in range(nx):
+            out[self.members[s]] = x[s]
+        return out

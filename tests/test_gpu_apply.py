@@ -193,48 +193,38 @@ def test_rhs_parity(face):
     assert _rel(b, ref) <= 1e-13
 
 
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_full_size_sheared_box_whole_vector(p):
+    """The operator sweep workload at full size (~4.2M dofs), the benchmark's launch: the whole
+    output vs the oracle's apply, FP64 and FP32, unconstrained and constrained (x- and z+
+    faces clamped), over all dofs and over the nodes of each single material."""
+    import fullsize
+    pa = _pa()
+    lam, mu = fullsize.lame(p)
+    x = fullsize.x_vec(p)
+    for clamped, flags in ((False, pa.PA_UNCONSTRAINED), (True, 0)):
+        print(f"full-size sheared box p={p} clamped={clamped}: oracle", flush=True)
+        ref = fullsize.oracle_apply(p, clamped)
+        for dtype in (0, 1):
+            y, op = _gpu_apply(fullsize.mesh(p, clamped), p, p + 2, lam, mu, x, dtype, flags=flags)
+            fullsize.check_whole_vector(y, ref, p, dtype, f"p={p} dtype={dtype} clamped={clamped}")
+            del op
+
+
 @pytest.mark.parametrize("p", [1, 2, 4, 6, 8])
 @pytest.mark.parametrize("dtype", [0, 1])
-def test_full_size_sheared_box_sampled(p, dtype):
-    """The operator sweep workload at full size (~4.2M dofs), same launch as the benchmark:
-    sampled outputs vs the oracle computed element by element around the sampled nodes."""
+def test_full_size_translations_in_nullspace(p, dtype):
+    """A property that holds at any size: translations are in the nullspace of the
+    unconstrained operator on the full-size box."""
+    import fullsize
     pa = _pa()
-    print(f"full-size sheared box p={p} dtype={dtype}", flush=True)
-    mesh = syn.sheared_box_mesh(p)
-    NE = mesh.num_elements
-    lam, mu = syn.two_material_lame(NE, seed=1)
-    x = syn.uniform_vector(mesh.num_dofs(p), seed=0)
-    y, op = _gpu_apply(mesh, p, p + 2, lam, mu, x, dtype, flags=pa.PA_UNCONSTRAINED)
-    # oracle on the elements touching a sample of nodes
-    Kl, Km = elasticity.element_matrix_parts(p, p + 2, omesh.element_jacobians(syn.BoxMesh(n=(1, 1, 1), L=(
-        mesh.L[0] / mesh.n[0], mesh.L[1] / mesh.n[1], mesh.L[2] / mesh.n[2]), A=mesh.A))[0])
-    Nx, Ny, Nz = omesh.grid_shape(mesh, p)
-    rng = np.random.default_rng(2)
-    nodes = rng.integers(0, Nx * Ny * Nz, 40)
-    Nn = Nx * Ny * Nz
-    D = p + 1
-    for node in nodes:
-        gx, gy, gz = node % Nx, (node // Nx) % Ny, node // (Nx * Ny)
-        acc = np.zeros(3)
-        for ex in {min(gx // p, mesh.n[0] - 1), (gx - 1) // p if gx % p == 0 and gx > 0 else -1}:
-            for ey in {min(gy // p, mesh.n[1] - 1), (gy - 1) // p if gy % p == 0 and gy > 0 else -1}:
-                for ez in {min(gz // p, mesh.n[2] - 1), (gz - 1) // p if gz % p == 0 and gz > 0 else -1}:
-                    if min(ex, ey, ez) < 0:
-                        continue
-                    e = ex + mesh.n[0] * (ey + mesh.n[1] * ez)
-                    iz, iy, ix = np.meshgrid(np.arange(D), np.arange(D), np.arange(D), indexing="ij")
-                    gnodes = (ex * p + ix.ravel()) + Nx * ((ey * p + iy.ravel()) + Ny * (ez * p + iz.ravel()))
-                    xe = np.concatenate([x[c * Nn + gnodes] for c in range(3)])
-                    ye = (lam[e] * Kl + mu[e] * Km) @ xe
-                    a = (gx - ex * p) + D * ((gy - ey * p) + D * (gz - ez * p))
-                    acc += ye[[a, D ** 3 + a, 2 * D ** 3 + a]]
-        got = y[[node, Nn + node, 2 * Nn + node]]
-        scale = np.abs(y).max()
-        assert np.abs(got - acc).max() <= 50 * TOL[dtype] * scale, (node, got, acc)
-    # a property that holds at any size: translations are in the nullspace
+    lam, mu = fullsize.lame(p)
+    mesh = fullsize.mesh(p)
+    op = pa.Operator(mesh, p, lam, mu, q=p + 2, dtype=dtype)
     tdt = torch.float64 if dtype == 0 else torch.float32
-    xt = torch.tensor(x, dtype=tdt, device="cuda")
+    xt = torch.tensor(fullsize.x_vec(p), dtype=tdt, device="cuda")
     nrm = float(torch.linalg.norm(op.apply(xt, flags=pa.PA_UNCONSTRAINED)) / torch.linalg.norm(xt))
+    Nn = op.N // 3
     for c in range(3):
         u = torch.zeros(op.N, dtype=tdt, device="cuda")
         u[c * Nn:(c + 1) * Nn] = 1

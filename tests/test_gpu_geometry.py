@@ -190,3 +190,47 @@ def test_geometry_errors():
         with pytest.raises(pa.PaError) as ei:
             call()
         assert ei.value.code == pa.capi.PA_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("p", [1, 2, 4, 8])
+def test_geometry_full_size_whole_vector(p):
+    """The operator sweep's full-size sheared box (~4.2M dofs), the benchmark's launch, with its
+    exact vertices given to both trilinear forms: the trilinear map of a parallelepiped is
+    the affine map, so both equal the operator the oracle applies to the sweep workload.
+    The whole output vs the oracle, FP64 and FP32, over all dofs and each material's nodes."""
+    import fullsize
+    pa = _pa()
+    mesh = fullsize.mesh(p)
+    lam, mu = fullsize.lame(p)
+    x = fullsize.x_vec(p)
+    verts = syn.perturbed_vertices(mesh, amp=0.0)
+    print(f"geometry full size whole vector p={p}: oracle", flush=True)
+    ref = fullsize.oracle_apply(p)
+    for kind in KINDS:
+        for dtype in (0, 1):
+            op = pa.Operator.with_geometry(mesh, p, verts, lam, mu, kind=kind, dtype=dtype)
+            y = _gpu(op, x, pa.PA_UNCONSTRAINED)
+            op.close()
+            fullsize.check_whole_vector(y, ref, p, dtype, f"geometry kind={kind} p={p} dtype={dtype}")
+
+
+@pytest.mark.parametrize("p", [1, 2, 4, 8])
+def test_geometry_eighth_box_whole_vector(p):
+    """The distorted first 1/8 of the sweep's box (~0.5M dofs, interior vertices moved by up
+    to 0.2 of the spacing): both geometry forms, the whole output vs the oracle's quadrature
+    sum with per-point Jacobians, FP64 and FP32."""
+    import fullsize
+    pa = _pa()
+    sub = fullsize.eighth(p)
+    lam, mu = fullsize.eighth_lame(p)
+    print(f"geometry 1/8 box p={p}: oracle", flush=True)
+    ref = fullsize.eighth_trilinear_oracle(p)
+    x = fullsize.eighth_x(p)
+    for kind in KINDS:
+        for dtype in (0, 1):
+            op = pa.Operator.with_geometry(sub, p, fullsize.eighth_vertices(p), lam, mu, kind=kind, dtype=dtype)
+            y = _gpu(op, x, pa.PA_UNCONSTRAINED)
+            op.close()
+            err = _rel(y, ref)
+            print(f"  kind={kind} dtype={dtype}: rel err {err:.2e}", flush=True)
+            assert err <= TOL[dtype], err

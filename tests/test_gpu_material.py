@@ -55,7 +55,7 @@ def _gpu(op, x, flags):
     return y.double().cpu().numpy()
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 8])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("kind", [1, 2])
 @pytest.mark.parametrize("dtype", [0, 1])
 def test_material_parity(p, kind, dtype):
@@ -339,3 +339,61 @@ def test_qp_material_full_cantilever():
     defl = -xh.reshape(3, -1)[2, np.isclose(R[:, 0], 8.0)].mean()
     assert 0.9 * 2048 < defl < 1.1 * 2048 * 1.012, defl
     print(f"  iters {info.iters} tip {defl:.1f} t_solve {info.t_solve:.3f}s")
+
+
+@pytest.mark.parametrize("p", [1, 2, 4, 8])
+def test_material_full_size_whole_vector(p):
+    """The operator sweep's full-size sheared box (~4.2M dofs), the benchmark's launch, with
+    the two per-element materials carried by the general forms: per-point data constant over
+    each element's points, and each element's isotropic Voigt stiffness as an anisotropic C.
+    Both are the operator the oracle applies to the sweep workload: the whole output vs the
+    oracle, FP64 and FP32, over all dofs and over each single-material node set."""
+    import fullsize
+    pa = _pa()
+    mesh = fullsize.mesh(p)
+    NE, q = mesh.num_elements, p + 2
+    lam, mu = fullsize.lame(p)
+    x = fullsize.x_vec(p)
+    print(f"material full size whole vector p={p}: oracle", flush=True)
+    ref = fullsize.oracle_apply(p)
+    qp = np.empty((NE, q ** 3, 2))
+    qp[..., 0] = lam[:, None]
+    qp[..., 1] = mu[:, None]
+    forms = ((pa.PA_MAT_QP_ISO, qp), (pa.PA_MAT_ANISO, material.packed_upper(material.isotropic_voigt(lam, mu))))
+    for kind, data in forms:
+        for dtype in (0, 1):
+            op = pa.Operator.with_material(mesh, p, kind, data, dtype=dtype)
+            y = _gpu(op, x, pa.PA_UNCONSTRAINED)
+            op.close()
+            fullsize.check_whole_vector(y, ref, p, dtype, f"material kind={kind} p={p} dtype={dtype}")
+
+
+@pytest.mark.parametrize("p", [1, 2, 4, 8])
+@pytest.mark.parametrize("kind", [1, 2])
+def test_material_eighth_box_whole_vector(p, kind):
+    """General material data on the first 1/8 of the sweep's box (~0.5M dofs; many more
+    workgroups than the GPU has compute units): random per-point (lambda, mu) (two
+    materials x (1 +- 0.3 u)) or a random anisotropic C per element; the whole output vs
+    the oracle's strain-displacement form, FP64 and FP32, unconstrained."""
+    import fullsize
+    pa = _pa()
+    sub = fullsize.eighth(p)
+    NE, q = sub.num_elements, p + 2
+    print(f"material 1/8 box p={p} kind={kind}: oracle", flush=True)
+    if kind == pa.PA_MAT_QP_ISO:
+        lam_e, mu_e = fullsize.eighth_lame(p)
+        lam, mu = syn.quadrature_point_lame(lam_e, mu_e, q, seed=4)
+        data, C = np.stack([lam, mu], axis=-1), material.isotropic_voigt(lam, mu)
+    else:
+        C = syn.random_spd_stiffness(NE, seed=5)
+        data = material.packed_upper(C)
+    x = fullsize.eighth_x(p)
+    ref = material.GeneralOperator(sub, p, q, C).apply(x)
+    del C
+    for dtype in (0, 1):
+        op = pa.Operator.with_material(sub, p, kind, data, dtype=dtype)
+        y = _gpu(op, x, pa.PA_UNCONSTRAINED)
+        op.close()
+        err = _rel(y, ref)
+        print(f"  dtype={dtype}: rel err {err:.2e}", flush=True)
+        assert err <= TOL[dtype], err

@@ -200,3 +200,57 @@ def test_unstructured_errors():
         with pytest.raises(pa.PaError) as ei:
             call()
         assert ei.value.code == pa.capi.PA_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("p", [1, 2, 4, 8])
+def test_unstructured_full_size_whole_vector(p):
+    """The operator sweep's full-size sheared box (~4.2M dofs) with its exact vertices, written
+    as an unstructured mesh (elements in random order, each in a random orientation, box node
+    numbering): the same operator as the oracle's on the sweep workload.  The whole output
+    (mapped back to box nodes) vs the oracle, FP64 and FP32, over all dofs and each
+    material's nodes."""
+    import fullsize
+    pa = _pa()
+    mesh = fullsize.mesh(p)
+    lam, mu = fullsize.lame(p)
+    x = fullsize.x_vec(p)
+    verts = syn.perturbed_vertices(mesh, amp=0.0)
+    hm, node_map, order = syn.box_as_unstructured(mesh, verts, p, seed=3, permute=True, renumber=False)
+    Nn = mesh.num_nodes(p)
+    perm = np.concatenate([c * Nn + node_map for c in range(3)])   # unstructured dof -> box dof
+    print(f"unstructured full size whole vector p={p}: oracle", flush=True)
+    ref = fullsize.oracle_apply(p)
+    for dtype in (0, 1):
+        op = pa.Operator.unstructured(hm, lam[order], mu[order], dtype=dtype)
+        yu = _gpu(op, x[perm], pa.PA_UNCONSTRAINED)
+        op.close()
+        y = np.empty_like(yu)
+        y[perm] = yu
+        fullsize.check_whole_vector(y, ref, p, dtype, f"unstructured p={p} dtype={dtype}")
+
+
+@pytest.mark.parametrize("p", [1, 2, 4, 8])
+def test_unstructured_eighth_box_whole_vector(p):
+    """The distorted first 1/8 of the sweep's box (~0.5M dofs) as an unstructured mesh with
+    elements and nodes shuffled and every element in a random orientation: the whole output
+    (mapped back to box nodes) vs the oracle's quadrature sum on the box, FP64 and FP32."""
+    import fullsize
+    pa = _pa()
+    sub = fullsize.eighth(p)
+    lam, mu = fullsize.eighth_lame(p)
+    x = fullsize.eighth_x(p)
+    hm, node_map, order = syn.box_as_unstructured(sub, fullsize.eighth_vertices(p), p, seed=4, permute=True,
+                                                  renumber=False, shuffle_nodes=True)
+    Nn = sub.num_nodes(p)
+    perm = np.concatenate([c * Nn + node_map for c in range(3)])
+    print(f"unstructured 1/8 box p={p}: oracle", flush=True)
+    ref = fullsize.eighth_trilinear_oracle(p)
+    for dtype in (0, 1):
+        op = pa.Operator.unstructured(hm, lam[order], mu[order], dtype=dtype)
+        yu = _gpu(op, x[perm], pa.PA_UNCONSTRAINED)
+        op.close()
+        y = np.empty_like(yu)
+        y[perm] = yu
+        err = _rel(y, ref)
+        print(f"  dtype={dtype}: rel err {err:.2e}", flush=True)
+        assert err <= TOL[dtype], err

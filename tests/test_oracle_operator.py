@@ -210,3 +210,37 @@ def test_body_force_sum_graded():
     F = elasticity.body_force_vector(mesh, 3, 5, (1.0, 2.0, -3.0)).reshape(3, -1)
     vol = np.linalg.det(mesh.A) * 2.0 * 1.0 * 0.5
     assert np.allclose(F.sum(1), np.array([1.0, 2.0, -3.0]) * vol, rtol=1e-13)
+
+
+@pytest.mark.parametrize("face", [1, 2, 5])
+def test_traction_nodal_values_closed_form(face):
+    """On a graded sheared box the traction load on a face node is t times the face area
+    factor |A e_1 x A e_2| times, per in-face axis, the sum over the adjacent element edges of
+    h_e w_i (GLL weights: the integral of each 1D Lagrange factor), and zero off the face;
+    its first moments are t times the integrals of the in-face reference coordinates."""
+    mesh = syn.graded_mesh((3, 2, 4), seed=8, L=(1.1, 0.7, 1.4), A=syn.SHEAR_A)
+    p = 3
+    t = np.array([0.4, -1.0, 0.7])
+    F = elasticity.traction_vector(mesh, p, p + 2, face, t).reshape(3, -1)
+    axis, side = face // 2, face % 2
+    t1, t2 = [a for a in range(3) if a != axis]
+    w = rules.gll_weights(p)
+    ax = []
+    for a in (t1, t2):
+        X = mesh.axis_nodes(a)
+        s = np.zeros(mesh.n[a] * p + 1)
+        for e in range(mesh.n[a]):
+            s[e * p:e * p + p + 1] += w * (X[e + 1] - X[e])
+        ax.append(s)
+    area = np.linalg.norm(np.cross(mesh.A[:, t1], mesh.A[:, t2]))
+    shape = omesh.grid_shape(mesh, p)
+    idx = np.indices(shape[::-1]).reshape(3, -1)[::-1]          # (gx, gy, gz) of every node
+    on = idx[axis] == (0 if side == 0 else shape[axis] - 1)
+    expect = np.zeros(idx.shape[1])
+    expect[on] = area * ax[0][idx[t1][on]] * ax[1][idx[t2][on]]
+    for c in range(3):
+        assert np.allclose(F[c], t[c] * expect, rtol=1e-13, atol=1e-15)
+    # first moments: sum_a F_a X_a = t * area * int X dX over the face (reference coordinates)
+    g1 = omesh.axis_node_coords(mesh, t1, p)[idx[t1]]
+    L1, L2 = mesh.axis_nodes(t1)[-1], mesh.axis_nodes(t2)[-1]
+    assert np.allclose((F * g1).sum(1), t * area * 0.5 * L1 ** 2 * L2, rtol=1e-12)

@@ -142,3 +142,76 @@ def test_pcg_matches_direct():
     xs = np.linalg.solve(A, b)
     assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
     assert it < 40
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+@pytest.mark.parametrize("lo_frac", [0.1, 0.3])
+def test_chebyshev_error_polynomial(k, lo_frac):
+    """The smoother is exactly the Chebyshev polynomial of the interval: with D^{-1}A =
+    D^{-1/2} V diag(l) V^T D^{1/2} (A v = l D v), the error after k steps is
+    e_k = D^{-1/2} V diag(T_k((theta - l)/delta) / T_k(theta/delta)) V^T D^{1/2} e_0,
+    theta, delta the centre and half-width of [lmin, lmax] (here an interval that does not
+    contain the whole spectrum, as in the multigrid smoother, so T_k is evaluated inside
+    and outside [-1, 1])."""
+    mesh = syn.BoxMesh(n=(2, 2, 1), clamped_faces=1)
+    op, A, d = _system(mesh, 2, 1.3, 0.6)
+    sq = np.sqrt(d)
+    lam, V = np.linalg.eigh(A / np.outer(sq, sq))
+    lmax = 1.2 * lam[-1]
+    lmin = lo_frac * lmax
+    theta, delta = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+
+    def T(n, t):   # Chebyshev polynomial of the first kind by its three-term recurrence
+        a, b = np.ones_like(t), t
+        if n == 0:
+            return a
+        for _ in range(n - 1):
+            a, b = b, 2 * t * b - a
+        return b
+
+    rng = np.random.default_rng(10 + k)
+    xstar = rng.uniform(-1, 1, op.N)
+    b = A @ xstar
+    x0 = rng.uniform(-1, 1, op.N)
+    xk = solvers.chebyshev_smooth(A, d, b, x0, k, lmin, lmax)
+    pk = T(k, (theta - lam) / delta) / T(k, np.array(theta / delta))
+    ek = (V @ (pk * (V.T @ (sq * (x0 - xstar))))) / sq
+    assert np.linalg.norm((xk - xstar) - ek) <= 1e-11 * np.linalg.norm(x0 - xstar)
+
+
+def test_abs_apply_is_the_sum_of_element_magnitudes():
+    """abs_apply = sum_e G_e^T |K^e| G_e x assembled densely from the element matrices (two
+    materials, a graded sheared mesh), and |A x| <= abs_apply(|x|) entrywise; constrained
+    form: 0 on clamped columns, the input on clamped rows."""
+    mesh = syn.graded_mesh((3, 2, 2), seed=5, A=syn.SHEAR_A, clamped_faces=0b000101)
+    p = 2
+    lam, mu = syn.two_material_lame(mesh.num_elements, seed=3)
+    op = elasticity.Operator(mesh, p, p + 2, lam, mu)
+    M = np.zeros((op.N, op.N))
+    for e in range(mesh.num_elements):
+        d = op.edofs[e]
+        M[np.ix_(d, d)] += np.abs(op.element_matrix(e))
+    x = syn.uniform_vector(op.N, 4)
+    assert np.allclose(op.abs_apply(x), M @ x, rtol=1e-13, atol=1e-13 * np.abs(M @ x).max())
+    assert np.all(np.abs(op.apply(x)) <= op.abs_apply(np.abs(x)) * (1 + 1e-12) + 1e-14)
+    xc = x.copy()
+    xc[op.ess] = 0.0
+    ref = M @ xc
+    ref[op.ess] = x[op.ess]
+    assert np.allclose(op.abs_apply(x, constrained=True), ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("n,p,faces", [((4, 1, 1), 2, 1), ((3, 2, 2), 3, 0b100001), ((5, 2, 1), 1, 0b010011),
+                                       ((2, 1, 1), 4, 1), ((1, 1, 1), 2, 0b000010), ((3, 1, 2), 2, 0b000110)])
+def test_slab_cholesky_matches_dense_solve(n, p, faces):
+    """The block solve over x-slabs equals the dense solve of the assembled constrained system
+    (graded, rotated, sheared mesh, two materials, clamped faces across several blocks); clamped
+    entries of the solution equal those of the right-hand side (identity rows)."""
+    mesh = syn.graded_mesh(n, seed=3, A=syn.random_rotation(2) @ syn.SHEAR_A, clamped_faces=faces)
+    lam, mu = syn.two_material_lame(mesh.num_elements, seed=2)
+    op = elasticity.Operator(mesh, p, p + 2, lam, mu)
+    b = syn.uniform_vector(op.N, 1)
+    x = solvers.SlabCholesky(op).solve(b)
+    xr = np.linalg.solve(op.dense(constrained=True), b)
+    assert np.linalg.norm(x - xr) <= 1e-12 * np.linalg.norm(xr)
+    assert np.array_equal(x[op.ess], b[op.ess])
