@@ -72,6 +72,8 @@ extern "C" {
 #define PA_VARIANT_UNFUSED_DENSE 1    /* three passes, dense gradient/action, full-tensor stress   */
 #define PA_VARIANT_UNFUSED_SF 2       /* three passes, sum-factorized gradient/action              */
 #define PA_VARIANT_UNFUSED_SF_VOIGT 3 /* as 2 with the Voigt stress form                           */
+#define PA_VARIANT_FUSED_UNSTAGED 4   /* the three passes of 3 fused into one kernel per element,
+                                         quadrature-point data staged per element (Alg. 2)     */
 
 /* ---- solver modes / stopping tests ----------------------------------------- */
 #define PA_SOLVE_F64 0        /* FP64 PCG with an FP64 V-cycle                                */
@@ -225,10 +227,15 @@ int pa_elast_apply(pa_op_t* op, const void* x, void* y);
 /* As pa_elast_apply with flags PA_UNCONSTRAINED and/or PA_ADD (async). */
 int pa_elast_apply_ex(pa_op_t* op, const void* x, void* y, int flags);
 
-/* The same operator in the unfused forms of the paper's cumulative ablation
+/* The same operator in the earlier forms of the paper's cumulative ablation
  * (Sec. 4.1-4.4, ablation table; baseline dataflow Alg. 1): a gradient pass, a
  * stress pass and an action pass with operator-wide quadrature-point arrays in
- * device memory between them, then a fixed-order assembly.  For measurement;
+ * device memory between them, then a fixed-order assembly; PA_VARIANT_FUSED_UNSTAGED
+ * runs the sum-factorized passes and the Voigt stress in one kernel (macro-kernel
+ * fusion, Sec. 4.2, Alg. 2), each workgroup staging its elements' quadrature-point
+ * data (9 words per point) in its own part of a work array, then the same
+ * assembly -- the production apply adds the slice-wise organisation (Sec. 4.5).
+ * For measurement;
  * results equal pa_elast_apply_ex up to rounding.  FP64 operators with q = p+2
  * only (PA_EUNSUPPORTED otherwise); flags 0 or PA_UNCONSTRAINED (y is
  * overwritten).  The first call on an operator allocates its work arrays

@@ -13,7 +13,15 @@
 // every quadrature point, O(D^3 Q^3) per element, with the basis-gradient table
 // streamed from memory) or sum-factorized (X/Y/Z sweeps through LDS, one
 // workgroup per few elements); the stress pass uses full 3x3 tensors or the Voigt
-// form.  The production apply fuses all of this into one kernel.
+// form.
+// The fused variant (the fusion stage, Sec. 4.2, Alg. 2) runs the same three
+// sum-factorized/Voigt passes inside one kernel, element by element: each
+// workgroup stages its elements' quadrature-point data (the per-element el_QVec of
+// the paper, 9 words per point) in a buffer of its own, rewrites it in place with
+// the stress, and contracts it back, then the same fixed-order assembly.  What it
+// lacks against the production apply is the slice-wise organisation (Sec. 4.5):
+// gradients held in registers per quadrature column instead of a staged array, x
+// read and y written straight from and to the L-vectors.
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -97,29 +105,20 @@ action_dense_kernel(const double* __restrict__ qs, const double* __restrict__ dp
 }
 
 // ---------------------------------------------------------------- stress pass
-template <int Q, bool VOIGT>
-__global__ void __launch_bounds__(256)
-stress_kernel(const double* __restrict__ ed, const double* __restrict__ tab, const double* __restrict__ qg,
-              double* __restrict__ qs, const int64_t npts, const int DQ) {
-    constexpr int Q3 = Q * Q * Q;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= npts) return;
-    const int64_t e = t / Q3;
-    const int al = (int)(t % Q3);
-    const double* w = tab + 2 * DQ;
-    const double W = w[al % Q] * w[(al / Q) % Q] * w[al / (Q * Q)];
-    const double* d = ed + e * kEdStride;
+// One quadrature point: in[c*3+m] = d u_c / d xi_m -> out[c*3+m] = Q_{c,m} = sum_i sigma_{c,i}
+// (J^{-1})_{m,i}, sigma from the weighted w*detJ*lambda, w*detJ*mu (eq. 7); in may equal out.
+template <bool VOIGT>
+__device__ __forceinline__ void point_stress(const double* __restrict__ d, double W, const double* in, double* out) {
     double Ji[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) Ji[k] = d[k];
     const double lam = W * d[9], mu = W * d[10];
-    const double* gi = qg + t * 9;
     double du[3][3];   // du[c][i] = d u_c / d x_i
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int i = 0; i < 3; ++i)
-            du[c][i] = Ji[0 * 3 + i] * gi[c * 3] + Ji[1 * 3 + i] * gi[c * 3 + 1] + Ji[2 * 3 + i] * gi[c * 3 + 2];
+            du[c][i] = Ji[0 * 3 + i] * in[c * 3] + Ji[1 * 3 + i] * in[c * 3 + 1] + Ji[2 * 3 + i] * in[c * 3 + 2];
     double s[3][3];
     if (VOIGT) {
         // six independent stress components
@@ -144,11 +143,27 @@ stress_kernel(const double* __restrict__ ed, const double* __restrict__ tab, con
 #pragma unroll
             for (int j = 0; j < 3; ++j) s[i][j] = (i == j ? lam * tr : 0.0) + 2.0 * mu * eps[i][j];
     }
-    double* o = qs + t * 9;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int m = 0; m < 3; ++m) o[c * 3 + m] = s[c][0] * Ji[m * 3 + 0] + s[c][1] * Ji[m * 3 + 1] + s[c][2] * Ji[m * 3 + 2];
+        for (int m = 0; m < 3; ++m) out[c * 3 + m] = s[c][0] * Ji[m * 3 + 0] + s[c][1] * Ji[m * 3 + 1] + s[c][2] * Ji[m * 3 + 2];
+}
+
+template <int Q, bool VOIGT>
+__global__ void __launch_bounds__(256)
+stress_kernel(const double* __restrict__ ed, const double* __restrict__ tab, const double* __restrict__ qg,
+              double* __restrict__ qs, const int64_t npts, const int DQ) {
+    constexpr int Q3 = Q * Q * Q;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= npts) return;
+    const int64_t e = t / Q3;
+    const int al = (int)(t % Q3);
+    const double* w = tab + 2 * DQ;
+    const double W = w[al % Q] * w[(al / Q) % Q] * w[al / (Q * Q)];
+    double in[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) in[k] = qg[t * 9 + k];
+    point_stress<VOIGT>(ed + e * kEdStride, W, in, qs + t * 9);
 }
 
 // ---------------------------------------------------------------- sum-factorized passes
@@ -162,15 +177,16 @@ struct AbCfg {
     static constexpr int E = kAbT / WORK > 0 ? kAbT / WORK : 1;
 };
 
-template <int P, int Q>
-__global__ void __launch_bounds__(kAbT)
-grad_sf_kernel(const double* __restrict__ x, const double* __restrict__ tab, double* __restrict__ qg, const Geom g) {
-    constexpr int D = P + 1, Q3 = Q * Q * Q, E = AbCfg<P, Q>::E;
-    __shared__ double U[E][2][D][D][Q];    // x-contracted: B (value), G (derivative)
-    __shared__ double S[E][3][D][Q][Q];    // y-contracted: (G_x B_y), (B_x G_y), (B_x B_y)
+// Gradient pass of the elements e0 .. e0+E-1: for each component, X sweep from the
+// L-vector into U, Y sweep into S, Z sweep into qg[e][alpha][c*3+m] (the element's slice
+// of an array with 9 words per point).  U and S are the workgroup's LDS tiles.
+template <int P, int Q, int E>
+__device__ void grad_sf(const double* __restrict__ x, const double* __restrict__ tab, double* __restrict__ qg,
+                        const Geom& g, int e0, double (*U)[2][P + 1][P + 1][Q], double (*S)[3][P + 1][Q][Q]) {
+    constexpr int D = P + 1, Q3 = Q * Q * Q;
     const double* B = tab;
     const double* G = tab + D * Q;
-    const int e0 = blockIdx.x * E, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     const size_t NN = (size_t)g.Nn;
     for (int c = 0; c < 3; ++c) {
         for (int w = tid; w < E * D * D; w += kAbT) {
@@ -234,16 +250,15 @@ grad_sf_kernel(const double* __restrict__ x, const double* __restrict__ tab, dou
     }
 }
 
-template <int P, int Q>
-__global__ void __launch_bounds__(kAbT)
-action_sf_kernel(const double* __restrict__ qs, const double* __restrict__ tab, double* __restrict__ ev,
-                 const Geom g) {
-    constexpr int D = P + 1, D3 = D * D * D, Q3 = Q * Q * Q, E = AbCfg<P, Q>::E;
-    __shared__ double T[E][3][D][Q][Q];    // after backward Z: channels m = 0, 1 (B_z), 2 (G_z)
-    __shared__ double R[E][2][D][D][Q];    // after backward Y: G_x channel, B_x channel
+// Action pass of the elements e0 .. e0+E-1: for each component, backward Z from
+// qs[e][alpha][c*3+m] into T, backward Y into R, backward X into the element vectors ev.
+template <int P, int Q, int E>
+__device__ void action_sf(const double* __restrict__ qs, const double* __restrict__ tab, double* __restrict__ ev,
+                          const Geom& g, int e0, double (*T)[3][P + 1][Q][Q], double (*R)[2][P + 1][P + 1][Q]) {
+    constexpr int D = P + 1, D3 = D * D * D, Q3 = Q * Q * Q;
     const double* B = tab;
     const double* G = tab + D * Q;
-    const int e0 = blockIdx.x * E, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     for (int c = 0; c < 3; ++c) {
         for (int w = tid; w < E * Q * Q; w += kAbT) {
             const int el = w / (Q * Q), qy = (w % (Q * Q)) / Q, qx = w % Q, e = e0 + el;
@@ -289,6 +304,52 @@ action_sf_kernel(const double* __restrict__ qs, const double* __restrict__ tab, 
         }
         __syncthreads();
     }
+}
+
+template <int P, int Q>
+__global__ void __launch_bounds__(kAbT)
+grad_sf_kernel(const double* __restrict__ x, const double* __restrict__ tab, double* __restrict__ qg, const Geom g) {
+    constexpr int D = P + 1, E = AbCfg<P, Q>::E;
+    __shared__ double U[E][2][D][D][Q];    // x-contracted: B (value), G (derivative)
+    __shared__ double S[E][3][D][Q][Q];    // y-contracted: (G_x B_y), (B_x G_y), (B_x B_y)
+    grad_sf<P, Q, E>(x, tab, qg, g, blockIdx.x * E, U, S);
+}
+
+template <int P, int Q>
+__global__ void __launch_bounds__(kAbT)
+action_sf_kernel(const double* __restrict__ qs, const double* __restrict__ tab, double* __restrict__ ev,
+                 const Geom g) {
+    constexpr int D = P + 1, E = AbCfg<P, Q>::E;
+    __shared__ double T[E][3][D][Q][Q];    // after backward Z: channels m = 0, 1 (B_z), 2 (G_z)
+    __shared__ double R[E][2][D][D][Q];    // after backward Y: G_x channel, B_x channel
+    action_sf<P, Q, E>(qs, tab, ev, g, blockIdx.x * E, T, R);
+}
+
+// The fusion stage: gradient, Voigt stress and action of a workgroup's elements in one
+// kernel.  qv holds each element's quadrature-point data (9 words per point): the gradient
+// pass writes it, the stress rewrites it in place, the action pass reads it; it is written
+// and read back by the same workgroup only.  The two passes' LDS tiles share storage.
+template <int P, int Q>
+__global__ void __launch_bounds__(kAbT)
+fused_unstaged_kernel(const double* __restrict__ x, const double* __restrict__ ed, const double* __restrict__ tab,
+                      double* __restrict__ qv, double* __restrict__ ev, const Geom g) {
+    constexpr int D = P + 1, Q3 = Q * Q * Q, E = AbCfg<P, Q>::E;
+    __shared__ double S[E][3][D][Q][Q];    // Y-pass output, then backward Z output
+    __shared__ double U[E][2][D][D][Q];    // X-pass output, then backward Y output
+    const int e0 = blockIdx.x * E;
+    grad_sf<P, Q, E>(x, tab, qv, g, e0, U, S);
+    const double* w = tab + 2 * D * Q;
+    for (int t = threadIdx.x; t < E * Q3; t += kAbT) {
+        const int el = t / Q3, al = t % Q3, e = e0 + el;
+        if (e >= g.NE) continue;
+        double* pt = qv + ((size_t)e * Q3 + al) * 9;
+        double in[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) in[k] = pt[k];
+        point_stress<true>(ed + (size_t)e * kEdStride, w[al % Q] * w[(al / Q) % Q] * w[al / (Q * Q)], in, pt);
+    }
+    __syncthreads();
+    action_sf<P, Q, E>(qv, tab, ev, g, e0, S, U);
 }
 
 // ---------------------------------------------------------------- assembly
@@ -345,6 +406,14 @@ int run_variant(pa_op* op, AblationBuffers* b, const Geom& g, const double* x, d
     constexpr int D = P + 1, D3 = D * D * D, Q3 = Q * Q * Q;
     hipStream_t s = op->stream;
     const int64_t npts = (int64_t)g.NE * Q3;
+    if (variant == PA_VARIANT_FUSED_UNSTAGED) {
+        hipLaunchKernelGGL((fused_unstaged_kernel<P, Q>), dim3((g.NE + AbCfg<P, Q>::E - 1) / AbCfg<P, Q>::E),
+                           dim3(kAbT), 0, s, x, (const double*)op->ed, b->tab, b->qg, b->ev, g);
+        PA_HIP(hipGetLastError());
+        hipLaunchKernelGGL((assemble_kernel<P>), dim3(blocks_for(g.Nn)), dim3(256), 0, s, x, y, b->ev, g);
+        PA_HIP(hipGetLastError());
+        return PA_OK;
+    }
     if (variant == PA_VARIANT_UNFUSED_DENSE)
         hipLaunchKernelGGL((grad_dense_kernel<P, Q>), dim3(blocks_for(npts)), dim3(256), 0, s, x, b->dphi, b->qg, g);
     else
@@ -429,7 +498,7 @@ int prepare(pa_op* op) {
 int apply_variant(pa_op* op, const void* x, void* y, int flags, int variant) {
     if (variant == PA_VARIANT_FUSED) return apply_op(op, x, y, flags);
     if (variant != PA_VARIANT_UNFUSED_DENSE && variant != PA_VARIANT_UNFUSED_SF &&
-        variant != PA_VARIANT_UNFUSED_SF_VOIGT)
+        variant != PA_VARIANT_UNFUSED_SF_VOIGT && variant != PA_VARIANT_FUSED_UNSTAGED)
         return fail(PA_EINVAL, "unknown variant %d", variant);
     if (op->dtype != PA_F64) return fail(PA_EUNSUPPORTED, "the unfused variants are FP64 only");
     if (flags & PA_ADD) return fail(PA_EUNSUPPORTED, "the unfused variants overwrite y (no PA_ADD)");

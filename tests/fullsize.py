@@ -32,12 +32,12 @@ def lame(p: int):
     return syn.two_material_lame(syn.sheared_box_mesh(p).num_elements, seed=1)
 
 
-@functools.lru_cache(maxsize=4)
+@functools.lru_cache(maxsize=8)
 def x_vec(p: int) -> np.ndarray:
     return syn.uniform_vector(syn.sheared_box_mesh(p).num_dofs(p), seed=0)
 
 
-@functools.lru_cache(maxsize=6)
+@functools.lru_cache(maxsize=16)
 def oracle_apply(p: int, clamped: bool = False) -> np.ndarray:
     """The oracle's y = A x (constrained form when clamped) on the full-size box."""
     lam, mu = lame(p)
@@ -45,7 +45,7 @@ def oracle_apply(p: int, clamped: bool = False) -> np.ndarray:
     return op.apply(x_vec(p), constrained=clamped)
 
 
-@functools.lru_cache(maxsize=4)
+@functools.lru_cache(maxsize=8)
 def single_material_dofs(p: int):
     """(soft, stiff): dof masks of the nodes all of whose elements have E = 1 (soft) or
     all have E = 100 (stiff).  A wrong value at a node of the soft material is small
