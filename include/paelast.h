@@ -227,6 +227,23 @@ int pa_elast_apply(pa_op_t* op, const void* x, void* y);
 /* As pa_elast_apply with flags PA_UNCONSTRAINED and/or PA_ADD (async). */
 int pa_elast_apply_ex(pa_op_t* op, const void* x, void* y, int flags);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): pa_elast_apply_ex with the
+ * same kernels and results, whose element-boundary partial sums go to a static
+ * per-device scratch array of PA_NOALLOC_SCRATCH_BYTES bytes inside the library
+ * instead of the operator's buffer.  The call itself allocates nothing.  The array
+ * is set up when the first operator is created on a device (pa_elast_setup and the
+ * other setup calls) and stays allocated on every device the library runs on until
+ * the process ends.  Every operator whose element-boundary buffer fits is accepted;
+ * larger ones return PA_EINVAL with a message naming both sizes (at FP64, the
+ * sheared-box sweep of ~4.2M dofs fits at p = 1 and p >= 4).  Nothing in the array
+ * has to start at zero: an apply writes every entry it reads.  All calls on one
+ * device share the array and keep the last call's contents, so calls that overlap
+ * in time on one device (other streams, other host threads) race: serialise them.
+ * Flags, errors and stream as pa_elast_apply_ex (async). */
+#define PA_NOALLOC_SCRATCH_BYTES (64u << 20)
+int pa_elast_apply_noalloc(pa_op_t* op, const void* x, void* y, int flags);
+
 /* The same operator in the earlier forms of the paper's cumulative ablation
  * (Sec. 4.1-4.4, ablation table; baseline dataflow Alg. 1): a gradient pass, a
  * stress pass and an action pass with operator-wide quadrature-point arrays in

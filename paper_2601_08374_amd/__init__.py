@@ -199,6 +199,15 @@ class Operator:
         capi.check(capi.pa_elast_apply_ex(self.handle, C.c_void_p(_dptr(x)), C.c_void_p(_dptr(y)), int(flags)))
         return y
 
+    def apply_noalloc(self, x, y=None, flags: int = 0):
+        """pa_elast_apply_noalloc: the same apply with the library's static scratch array."""
+        if y is None:
+            y = self.empty()
+        assert x.dtype == self.torch_dtype and y.dtype == self.torch_dtype
+        assert x.numel() == self.N and y.numel() == self.N and x.is_contiguous() and y.is_contiguous()
+        capi.check(capi.pa_elast_apply_noalloc(self.handle, C.c_void_p(_dptr(x)), C.c_void_p(_dptr(y)), int(flags)))
+        return y
+
     def apply_variant(self, x, y=None, variant: int = 0, flags: int = 0):
         """pa_elast_apply_variant: the unfused ablation forms of the same operator."""
         if y is None:

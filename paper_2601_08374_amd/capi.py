@@ -25,6 +25,7 @@ PA_F64 = 0
 PA_F32 = 1
 PA_UNCONSTRAINED = 1
 PA_ADD = 2
+PA_NOALLOC_SCRATCH_BYTES = 64 << 20
 PA_VARIANT_FUSED = 0
 PA_VARIANT_UNFUSED_DENSE = 1
 PA_VARIANT_UNFUSED_SF = 2
@@ -85,6 +86,7 @@ SIGNATURES = {
     "pa_bytes_required": (C.c_int64, [C.POINTER(pa_mesh_t), _i, _i, _i]),
     "pa_elast_apply": (_i, [_vp, _vp, _vp]),
     "pa_elast_apply_ex": (_i, [_vp, _vp, _vp, _i]),
+    "pa_elast_apply_noalloc": (_i, [_vp, _vp, _vp, _i]),
     "pa_elast_apply_variant": (_i, [_vp, _vp, _vp, _i, _i]),
     "pa_elast_diagonal": (_i, [_vp, _vp, _i]),
     "pa_elast_rhs": (_i, [_vp, _dp, _i, _dp, _vp]),

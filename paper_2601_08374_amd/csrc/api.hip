@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "internal.h"
@@ -13,6 +14,37 @@
 namespace pa {
 
 static thread_local char g_err[1024] = "";
+
+// ---- scratch of pa_elast_apply_noalloc: the element-boundary partial sums of one apply
+// live in this array instead of the operator's own buffer.  Each device holds its own
+// copy until the process ends; host code never passes the array's name to a kernel, only
+// the device address looked up once per device.
+constexpr size_t kScratchBytes = (size_t)PA_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[kMaxDevices] = {};
+
+int scratch_address(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(PA_EUNSUPPORTED, "device %d is beyond the %d devices the library tracks", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return fail(PA_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+        if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess)
+            return fail(PA_EHIP, "hipSetDevice(%d): %s", dev, hipGetErrorString(e));
+        void* a = nullptr;
+        e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !a)
+            return fail(PA_EHIP, "address of the scratch array on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_addr[dev] = a;
+    }
+    *out = g_scratch_addr[dev];
+    return PA_OK;
+}
 
 int fail(int code, const char* fmt, ...) {
     va_list ap;
@@ -81,6 +113,7 @@ int create_op(const MeshDesc& md, int p, int q, const double* lam, const double*
     op->Nn = Nn;
     op->N = 3 * Nn;
     op->stream = s;
+    op->sk_bytes = (size_t)skeleton_words(p, md.n, lin_kernel) * (dtype == PA_F64 ? sizeof(double) : sizeof(float));
     op->lam.assign(lam, lam + NE);
     op->mu.assign(mu, mu + NE);
     pa_solve_opts_default(&op->cached_opts);
@@ -89,11 +122,15 @@ int create_op(const MeshDesc& md, int p, int q, const double* lam, const double*
     const size_t nvert = md.vert[0].size() + md.vert[1].size() + md.vert[2].size();
     const size_t esz = dtype == PA_F64 ? sizeof(double) : sizeof(float);
     do {
+        if (hipGetDevice(&op->device) != hipSuccess) {
+            rc = fail(PA_EHIP, "hipGetDevice failed");
+            break;
+        }
         rc = compute_tables(p, q, s, &op->d_tab, &op->tab);
         if (rc) break;
         if (hipMalloc(&op->d_vert, nvert * sizeof(double)) != hipSuccess ||
             hipMalloc(&op->ed, (size_t)NE * kEdStride * esz) != hipSuccess ||
-            hipMalloc(&op->sk, (size_t)skeleton_words(p, md.n, lin_kernel) * esz) != hipSuccess ||
+            hipMalloc(&op->sk, op->sk_bytes) != hipSuccess ||
             hipMalloc(&d_lm, 2 * (size_t)NE * sizeof(double)) != hipSuccess) {
             (void)hipGetLastError();
             rc = fail(PA_ENOMEM, "device allocation failed (%lld elements)", (long long)NE);
@@ -116,6 +153,9 @@ int create_op(const MeshDesc& md, int p, int q, const double* lam, const double*
         pa_elast_destroy(op);
         return rc;
     }
+    // set-up of the no-allocation apply on this device (a failure is reported by that entry point)
+    void* sa = nullptr;
+    (void)scratch_address(op->device, &sa);
     *out = op;
     return PA_OK;
 }
@@ -156,7 +196,7 @@ int check_material(int kind, const double* data, int64_t NE, int64_t per) {
     return PA_OK;
 }
 
-int apply_op(const pa_op* op, const void* x, void* y, int flags) {
+int apply_op(const pa_op* op, const void* x, void* y, int flags, void* sk) {
     const bool constrained = !(flags & PA_UNCONSTRAINED);
     const int add = (flags & PA_ADD) ? 1 : 0;
     ApplyLaunch L;
@@ -179,7 +219,7 @@ int apply_op(const pa_op* op, const void* x, void* y, int flags) {
     }
     L.x = x;
     L.y = y;
-    L.sk = op->sk;
+    L.sk = sk ? sk : op->sk;
     L.ed = op->ed;
     L.mat = op->mat;
     L.md = op->md;
@@ -378,6 +418,19 @@ int pa_elast_apply_ex(pa_op_t* op, const void* x, void* y, int flags) {
 }
 
 int pa_elast_apply(pa_op_t* op, const void* x, void* y) { return pa_elast_apply_ex(op, x, y, 0); }
+
+int pa_elast_apply_noalloc(pa_op_t* op, const void* x, void* y, int flags) {
+    if (!op || !x || !y) return fail(PA_EINVAL, "NULL argument");
+    if (x == y) return fail(PA_EINVAL, "x and y must not alias");
+    if (flags & ~(PA_UNCONSTRAINED | PA_ADD)) return fail(PA_EINVAL, "unknown flags 0x%x", flags);
+    if (op->sk_bytes > kScratchBytes)
+        return fail(PA_EINVAL, "the operator's element-boundary sums need %zu bytes, above the %zu-byte scratch of "
+                               "pa_elast_apply_noalloc (use pa_elast_apply_ex)", op->sk_bytes, kScratchBytes);
+    void* s = nullptr;
+    const int rc = scratch_address(op->device, &s);
+    if (rc) return rc;
+    return apply_op(op, x, y, flags, s);
+}
 
 int pa_elast_diagonal(pa_op_t* op, void* d, int flags) {
     if (!op || !d) return fail(PA_EINVAL, "NULL argument");

@@ -146,6 +146,8 @@ struct pa_op {
     std::vector<double> lam, mu;     // host copies (used to build solver hierarchies)
     void* ed = nullptr;              // device per-element data [NE][kEdStride] of dtype
     void* sk = nullptr;              // skeleton buffer (skeleton_words) of dtype used by every apply
+    size_t sk_bytes = 0;             // its size
+    int device = 0;                  // HIP device that holds the operator's memory
     double* d_tab = nullptr;         // device copy of the FP64 tables (B, G, w, bb/bg/gg, sB)
     double* d_vert = nullptr;        // device vertex coordinates, x | y | z
     pa::Tables tab;                  // host copy of the tables (kernel arguments)

@@ -72,6 +72,9 @@ int launch_set_clamped(void* y, int dtype, const Geom& g, double v, hipStream_t 
 int launch_apply_prep(const void* x, void* y, int dtype, const Geom& g, int add, hipStream_t s);
 
 // apply dispatch (api.hip)
-int apply_op(const pa_op* op, const void* x, void* y, int flags);
+// sk: skeleton buffer for this apply (nullptr: the operator's own)
+int apply_op(const pa_op* op, const void* x, void* y, int flags, void* sk = nullptr);
+// Look up the per-device address of the no-allocation scratch array (set-up).
+int scratch_address(int dev, void** out);
 
 }  // namespace pa

@@ -155,8 +155,10 @@ extern "C" int pa_elast_setup_unstructured(int64_t num_vertices, const double* v
     op->n_sk = n_sk;
     pa_solve_opts_default(&op->cached_opts);
     const size_t esz = dtype == PA_F64 ? sizeof(double) : sizeof(float);
-    int rc = compute_tables(p, q, op->stream, &op->d_tab, &op->tab);
-    if (!rc && hipMalloc(&op->sk, (size_t)NE * 3 * S * esz) != hipSuccess) {
+    op->sk_bytes = (size_t)NE * 3 * S * esz;
+    int rc = hipGetDevice(&op->device) == hipSuccess ? PA_OK : fail(PA_EHIP, "hipGetDevice failed");
+    if (!rc) rc = compute_tables(p, q, op->stream, &op->d_tab, &op->tab);
+    if (!rc && hipMalloc(&op->sk, op->sk_bytes) != hipSuccess) {
         (void)hipGetLastError();
         op->sk = nullptr;
         rc = fail(PA_ENOMEM, "device allocation of the skeleton buffer failed");
@@ -170,6 +172,9 @@ extern "C" int pa_elast_setup_unstructured(int64_t num_vertices, const double* v
         pa_elast_destroy(op);
         return rc;
     }
+    // set-up of the no-allocation apply on this device (a failure is reported by that entry point)
+    void* sa = nullptr;
+    (void)scratch_address(op->device, &sa);
     *out = op;
     return PA_OK;
 }
