@@ -65,55 +65,78 @@ __device__ __forceinline__ size_t lin_slot(int t, int c, int lz, int ly, int lx,
 // Inputs per component c and x-column ix: a = B_y B_z x, b = G_y B_z x, e = B_y G_z x.
 // QPM: per-point Lame parameters lq[qx], mq[qx] of the column scale lzy, mzy (which then
 // carry w det J only).
+//
+// With the linear basis in x, B_x(xi) = (1 - xi, xi) and G_x = (-1, 1), so along the
+// column the reference gradient is linear in xi: g = (a1 - a0, b0 + xi (b1 - b0),
+// e0 + xi (e1 - e0)), and so is the physical gradient, du = D0 + xi D1 (both J^{-T}
+// products formed once per column; du is still evaluated at every point).  On the way
+// back, J^{-1} is constant over the element, so the x sums of Q = sigma J^{-T} are
+// J^{-1} applied to the x sums of sigma: the points accumulate the moments
+// M0 = sum w sigma and M1 = sum w xi sigma (6 Voigt entries each), and
+// S0 = sum Q_0 = M0 J^{-1}_0, r_m = (sum (1 - xi) Q_m, sum xi Q_m) = ((M0 - M1) J^{-1}_m, M1 J^{-1}_m).
 template <int Q, typename T, bool QPM = false>
 __device__ __forceinline__ void lin_column(const T (&a)[3][2], const T (&b)[3][2], const T (&e)[3][2],
                                            const T (&Ji)[9], const T lzy, const T mzy, const LinTabs<T, Q>& tb,
                                            T (&S0)[3], T (&r1)[3][2], T (&r2)[3][2], const T* lq = nullptr,
                                            const T* mq = nullptr) {
+    T D0[3][3], D1[3][3];   // du[c][i] = d u_c / d x_i = D0[c][i] + xi D1[c][i]
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        S0[c] = T(0);
-        r1[c][0] = r1[c][1] = r2[c][0] = r2[c][1] = T(0);
+        const T ga = a[c][1] - a[c][0], db = b[c][1] - b[c][0], de = e[c][1] - e[c][0];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            D0[c][i] = Ji[0 * 3 + i] * ga + Ji[1 * 3 + i] * b[c][0] + Ji[2 * 3 + i] * e[c][0];
+            D1[c][i] = Ji[1 * 3 + i] * db + Ji[2 * 3 + i] * de;
+        }
     }
+    // Voigt moments: entries (xx, yy, zz, yz, xz, xy)
+    T M0[6], M1[6];
+#pragma unroll
+    for (int v = 0; v < 6; ++v) M0[v] = M1[v] = T(0);
 #pragma unroll
     for (int qx = 0; qx < Q; ++qx) {
-        const T bx0 = tb.B0[qx], bx1 = tb.B1[qx];
-        T g[3][3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            g[c][0] = a[c][1] - a[c][0];
-            g[c][1] = bx0 * b[c][0] + bx1 * b[c][1];
-            g[c][2] = bx0 * e[c][0] + bx1 * e[c][1];
-        }
+        const T xi = tb.B1[qx];
         const T lam = QPM ? lzy * tb.w[qx] * lq[qx] : lzy * tb.w[qx];
         const T mu = QPM ? mzy * tb.w[qx] * mq[qx] : mzy * tb.w[qx];
-        T du[3][3];   // du[c][i] = d u_c / d x_i = sum_m Jinv[m][i] g[c][m]
+        T du[3][3];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
-            for (int i = 0; i < 3; ++i)
-                du[c][i] = Ji[0 * 3 + i] * g[c][0] + Ji[1 * 3 + i] * g[c][1] + Ji[2 * 3 + i] * g[c][2];
+            for (int i = 0; i < 3; ++i) du[c][i] = fma(xi, D1[c][i], D0[c][i]);
         const T div = du[0][0] + du[1][1] + du[2][2];
         const T ld = lam * div, m2 = mu + mu;
-        T s[3][3];
-        s[0][0] = ld + m2 * du[0][0];
-        s[1][1] = ld + m2 * du[1][1];
-        s[2][2] = ld + m2 * du[2][2];
-        s[0][1] = s[1][0] = mu * (du[0][1] + du[1][0]);
-        s[0][2] = s[2][0] = mu * (du[0][2] + du[2][0]);
-        s[1][2] = s[2][1] = mu * (du[1][2] + du[2][1]);
-        // Q[c][m] = sum_i sigma[c][i] Jinv[m][i]; backward X
+        T sv[6];
+        sv[0] = ld + m2 * du[0][0];
+        sv[1] = ld + m2 * du[1][1];
+        sv[2] = ld + m2 * du[2][2];
+        sv[3] = mu * (du[1][2] + du[2][1]);
+        sv[4] = mu * (du[0][2] + du[2][0]);
+        sv[5] = mu * (du[0][1] + du[1][0]);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const T q0 = s[c][0] * Ji[0] + s[c][1] * Ji[1] + s[c][2] * Ji[2];
-            const T q1 = s[c][0] * Ji[3] + s[c][1] * Ji[4] + s[c][2] * Ji[5];
-            const T q2 = s[c][0] * Ji[6] + s[c][1] * Ji[7] + s[c][2] * Ji[8];
-            S0[c] += q0;
-            r1[c][0] += bx0 * q1;
-            r1[c][1] += bx1 * q1;
-            r2[c][0] += bx0 * q2;
-            r2[c][1] += bx1 * q2;
+        for (int v = 0; v < 6; ++v) {
+            M0[v] += sv[v];
+            M1[v] = fma(xi, sv[v], M1[v]);
         }
+    }
+    // sigma[c][i] as a Voigt index
+    constexpr int kV[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T s0 = T(0), R1 = T(0), X1 = T(0), R2 = T(0), X2 = T(0);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const T m0 = M0[kV[c][i]], m1 = M1[kV[c][i]];
+            s0 = fma(m0, Ji[0 * 3 + i], s0);
+            R1 = fma(m0, Ji[1 * 3 + i], R1);
+            X1 = fma(m1, Ji[1 * 3 + i], X1);
+            R2 = fma(m0, Ji[2 * 3 + i], R2);
+            X2 = fma(m1, Ji[2 * 3 + i], X2);
+        }
+        S0[c] = s0;
+        r1[c][0] = R1 - X1;
+        r1[c][1] = X1;
+        r2[c][0] = R2 - X2;
+        r2[c][1] = X2;
     }
 }
 
