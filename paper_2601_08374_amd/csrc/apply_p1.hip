@@ -459,21 +459,67 @@ pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ 
     emit_layer(v, ez1);
 }
 
-// For every node on a tile boundary: sum the partial sums of the tiles touching it
+// The nodes that more than one tile holds (on an interior tile plane x = 8k, y = 8k or
+// z = TZ k), numbered as three sets so that only they get lanes: (a) every node of the
+// interior x planes, (b) the nodes of the interior y planes off the x planes, (c) the nodes
+// of the interior z planes off the x and y planes.
+struct LinSharedNodes {
+    int nxp, nyp, nzp;    // interior tile planes along x, y, z
+    int64_t na, nb, nc;   // nodes in each set
+};
+
+inline LinSharedNodes lin_shared_nodes(const Geom& g, int TZ) {
+    LinSharedNodes s;
+    s.nxp = (g.nx + kLinTX - 1) / kLinTX - 1;
+    s.nyp = (g.ny + kLinTY - 1) / kLinTY - 1;
+    s.nzp = (g.nz + TZ - 1) / TZ - 1;
+    s.na = (int64_t)s.nxp * g.Ny * g.Nz;
+    s.nb = (int64_t)s.nyp * (g.Nx - s.nxp) * g.Nz;
+    s.nc = (int64_t)s.nzp * (g.Nx - s.nxp) * (g.Ny - s.nyp);
+    return s;
+}
+
+// j-th coordinate along an axis that is not on one of the np interior planes at multiples
+// of w (w coordinates before the first plane, w - 1 between two planes)
+__device__ __forceinline__ int off_plane(int j, int w, int np) {
+    return j < w ? j : j + min(np, 1 + (j - w) / (w - 1));
+}
+
+// For every shared tile-boundary node: sum the partial sums of the tiles touching it
 // in a fixed order (z, y, x candidates) and write y.
 template <typename T>
 __global__ void __launch_bounds__(256)
 pa_lin_skeleton_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ sk, const Geom g,
-                       const int TZ, const int add) {
-    const int node = blockIdx.x * blockDim.x + threadIdx.x;
-    if (node >= g.Nn) return;
-    const int gx = node % g.Nx, r = node / g.Nx;
-    const int gy = r % g.Ny, gz = r / g.Ny;
+                       const int TZ, const LinSharedNodes sn, const int add) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int gx, gy, gz;
+    if (t < sn.na) {
+        const int64_t r = t / sn.nxp;
+        gx = kLinTX * (int)(t % sn.nxp + 1);
+        gy = (int)(r % g.Ny);
+        gz = (int)(r / g.Ny);
+    } else if (t < sn.na + sn.nb) {
+        const int64_t u = t - sn.na;
+        const int64_t r = u / sn.nyp;
+        const int nxo = g.Nx - sn.nxp;
+        gy = kLinTY * (int)(u % sn.nyp + 1);
+        gx = off_plane((int)(r % nxo), kLinTX, sn.nxp);
+        gz = (int)(r / nxo);
+    } else if (t < sn.na + sn.nb + sn.nc) {
+        const int64_t u = t - sn.na - sn.nb;
+        const int64_t r = u / sn.nzp;
+        const int nxo = g.Nx - sn.nxp;
+        gz = TZ * (int)(u % sn.nzp + 1);
+        gx = off_plane((int)(r % nxo), kLinTX, sn.nxp);
+        gy = off_plane((int)(r / nxo), kLinTY, sn.nyp);
+    } else {
+        return;
+    }
+    const int node = gx + g.Nx * (gy + g.Ny * gz);
     const int gg[3] = {gx, gy, gz}, nn[3] = {g.nx, g.ny, g.nz}, TT[3] = {kLinTX, kLinTY, TZ};
     // per axis the tiles of the elements before (gg-1) and after (gg) the node
     int t_[3][2];
     bool v_[3][2];
-    bool single = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const bool lo = gg[a] > 0, hi = gg[a] < nn[a];
@@ -481,9 +527,7 @@ pa_lin_skeleton_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __re
         t_[a][1] = hi ? gg[a] / TT[a] : 0;
         v_[a][0] = lo;
         v_[a][1] = hi && !(lo && t_[a][1] == t_[a][0]);
-        single = single && !(v_[a][0] && v_[a][1]);
     }
-    if (single) return;   // every element of the node is in one tile: written by the apply kernel
     const int ntx = (g.nx + kLinTX - 1) / kLinTX, nty = (g.ny + kLinTY - 1) / kLinTY;
     const size_t NN = (size_t)g.Nn;
     const bool cl = g.clamp && clamped_node(g.clamp, gx, gy, gz, g);
@@ -499,10 +543,10 @@ pa_lin_skeleton_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __re
             for (int c = 0; c < 3; ++c) v[k][c] = T(0);
             if (v_[0][kx] && v_[1][ky] && v_[2][kz]) {
                 const int tx = t_[0][kx], ty = t_[1][ky], tz = t_[2][kz];
-                const int t = tx + ntx * (ty + nty * tz);
+                const int tl = tx + ntx * (ty + nty * tz);
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
-                    v[k][c] = sk[lin_slot(t, c, gz - tz * TZ, gy - ty * kLinTY, gx - tx * kLinTX, TZ)];
+                    v[k][c] = sk[lin_slot(tl, c, gz - tz * TZ, gy - ty * kLinTY, gx - tx * kLinTX, TZ)];
             }
         }
         // (an empty asm per value keeps the sums out of the branches above)
@@ -545,10 +589,13 @@ int launch_lin(const ApplyLaunch& L) {
     hipLaunchKernelGGL((pa_apply_lin_kernel<Q, T, QPM>), dim3(nb), dim3(256), 0, L.stream, (const T*)L.x, (T*)L.y,
                        (T*)L.sk, (const T*)L.ed, tb, g, tz, L.add, (const T*)L.md);
     PA_HIP(hipGetLastError());
-    const int nb2 = (g.Nn + 255) / 256;
-    hipLaunchKernelGGL((pa_lin_skeleton_kernel<T>), dim3(nb2), dim3(256), 0, L.stream, (const T*)L.x, (T*)L.y,
-                       (const T*)L.sk, g, tz, L.add);
-    PA_HIP(hipGetLastError());
+    const LinSharedNodes sn = lin_shared_nodes(g, tz);
+    const int64_t nsh = sn.na + sn.nb + sn.nc;
+    if (nsh > 0) {
+        hipLaunchKernelGGL((pa_lin_skeleton_kernel<T>), dim3((unsigned)((nsh + 255) / 256)), dim3(256), 0, L.stream,
+                           (const T*)L.x, (T*)L.y, (const T*)L.sk, g, tz, sn, L.add);
+        PA_HIP(hipGetLastError());
+    }
     return PA_OK;
 }
 
