@@ -420,8 +420,6 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
     __shared__ T Ua[E * UT];          // X-pass output | backward Y output
     __shared__ T Es[E * kEdStride];   // per-element PA data of the block
     __shared__ T Cs[MAT == kMatAniso || GEO == kGeoTri ? E * 21 : 1];   // stiffness or trilinear coefficients
-    __shared__ int ebase[E];          // first node of each element, or -1 past the end
-    __shared__ int ecoord[E][3];
     // unstructured: node ids of the element lines in registers, or (KL) the block's map in LDS
     constexpr bool KL = UNS && kUnsIdsInLds<P, T>;
     __shared__ int Ks[KL ? E * D * D * D : 1];
@@ -430,35 +428,6 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int e0 = blk * E;
     const int ne_blk = g.NE - e0 < E ? g.NE - e0 : E;
-    if (tid < E) {
-        const int e = e0 + tid;
-        if (UNS) {
-            ebase[tid] = e < g.NE ? 0 : -1;
-        } else if (e < g.NE) {
-            const int ex = e % g.nx, r = e / g.nx;
-            const int ey = r % g.ny, ez = r / g.ny;
-            ecoord[tid][0] = ex * P;
-            ecoord[tid][1] = ey * P;
-            ecoord[tid][2] = ez * P;
-            ebase[tid] = ex * P + g.Nx * (ey * P + g.Ny * ez * P);
-        } else {
-            ebase[tid] = -1;
-        }
-    }
-    if constexpr (KL) {
-        for (int w = tid; w < E * D * D * D; w += NT)
-            Ks[w] = w < ne_blk * (D * D * D) ? kmap[(size_t)e0 * (D * D * D) + w] : 0;
-    }
-    for (int w = tid; w < E * kEdStride; w += NT)
-        Es[w] = w < ne_blk * kEdStride ? ed[(size_t)e0 * kEdStride + w] : T(0);
-    if constexpr (MAT == kMatAniso) {
-        for (int w = tid; w < E * 21; w += NT) Cs[w] = w < ne_blk * 21 ? md[(size_t)e0 * 21 + w] : T(0);
-    }
-    if constexpr (GEO == kGeoTri) {
-        // slots past the last element repeat element e0 (a regular map; their Lame data is zero)
-        for (int w = tid; w < E * 21; w += NT) Cs[w] = gd[(size_t)e0 * 21 + (w < ne_blk * 21 ? w : w % 21)];
-    }
-
     const int cel = tid / QQ, cq = tid % QQ;
     const int cqx = cq % Q, cqy = cq / Q;
     const bool has_col = tid < E * QQ;
@@ -481,7 +450,10 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
         if constexpr (KL) return (unsigned)Ks[ln_node[j] + ix] & ~kClampBit;
         else return (size_t)ln_nodes[UNS ? j : 0][UNS ? ix : 0];
     };
-    __syncthreads();       // ebase, ecoord, Es, Ks ready
+    // the lines' node addresses and clamp flags come from the element numbers (from the
+    // block's map in LDS when KL), so that the first x loads are in flight while the
+    // element data is staged
+    auto line_setup = [&]() {
 #pragma unroll
     for (int j = 0; j < GX; ++j) {
         ln_node[j] = -1;
@@ -490,17 +462,17 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
         if (l < NL) {
             const int el = l / (D * D), r = l % (D * D);
             const int iz = r / D, iy = r % D;
-            const int b = ebase[el];
+            const bool valid = el < ne_blk;
             ln_slot[j] = SK::index(0, iy, iz);
             if (SK::full_row(iy, iz)) ln_full |= 1u << j;
-            if (KL && b >= 0) {
+            if (KL && valid) {
                 ln_node[j] = el * (D * D * D) + D * (iy + D * iz);
                 if (g.clamp) {
 #pragma unroll
                     for (int ix = 0; ix < D; ++ix)
                         if ((unsigned)Ks[ln_node[j] + ix] & kClampBit) ln_cl |= 1u << (j * D + ix);
                 }
-            } else if (UNS && b >= 0) {
+            } else if (UNS && valid) {
                 ln_node[j] = 0;
                 const int* mp = kmap + (size_t)(e0 + el) * (D * D * D) + D * (iy + D * iz);
 #pragma unroll
@@ -509,17 +481,20 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
                     ln_nodes[UNS && !KL ? j : 0][UNS && !KL ? ix : 0] = (int)(v & ~kClampBit);
                     if (g.clamp && (v & kClampBit)) ln_cl |= 1u << (j * D + ix);
                 }
-            } else if (b >= 0) {
-                ln_node[j] = b + g.Nx * (iy + g.Ny * iz);
+            } else if (valid) {
+                const int e = e0 + el;
+                const int ex = e % g.nx, er = e / g.nx;
+                const int gx0 = ex * P, gy0 = (er % g.ny) * P, gz0 = (er / g.ny) * P;
+                ln_node[j] = gx0 + g.Nx * (gy0 + iy + g.Ny * (gz0 + iz));
                 if (g.clamp) {
 #pragma unroll
                     for (int ix = 0; ix < D; ++ix)
-                        if (clamped_node(g.clamp, ecoord[el][0] + ix, ecoord[el][1] + iy, ecoord[el][2] + iz, g))
-                            ln_cl |= 1u << (j * D + ix);
+                        if (clamped_node(g.clamp, gx0 + ix, gy0 + iy, gz0 + iz, g)) ln_cl |= 1u << (j * D + ix);
                 }
             }
         }
     }
+    };
     T xr[GX][D];
     auto line_load = [&](int c) {
 #pragma unroll
@@ -530,7 +505,29 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
                                 ? x[c * NN + (UNS ? uns_node(j, ix) : (size_t)(ln_node[j] + ix))]
                                 : T(0);
     };
-    line_load(0);
+    if constexpr (!KL) {
+        line_setup();
+        line_load(0);
+    }
+    if constexpr (KL) {
+        for (int w = tid; w < E * D * D * D; w += NT)
+            Ks[w] = w < ne_blk * (D * D * D) ? kmap[(size_t)e0 * (D * D * D) + w] : 0;
+    }
+    for (int w = tid; w < E * kEdStride; w += NT)
+        Es[w] = w < ne_blk * kEdStride ? ed[(size_t)e0 * kEdStride + w] : T(0);
+    if constexpr (MAT == kMatAniso) {
+        for (int w = tid; w < E * 21; w += NT) Cs[w] = w < ne_blk * 21 ? md[(size_t)e0 * 21 + w] : T(0);
+    }
+    if constexpr (GEO == kGeoTri) {
+        // slots past the last element repeat element e0 (a regular map; their Lame data is zero)
+        for (int w = tid; w < E * 21; w += NT) Cs[w] = gd[(size_t)e0 * 21 + (w < ne_blk * 21 ? w : w % 21)];
+    }
+
+    __syncthreads();       // Es, Cs, Ks ready
+    if constexpr (KL) {
+        line_setup();
+        line_load(0);
+    }
 
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
