@@ -53,10 +53,19 @@ __device__ __forceinline__ void load_ed12(const float* p, float (&d)[12]) {
     }
 }
 
-// Slot of node (lx, ly, lz) of tile t (local node coordinates in the tile's node box;
-// tz = elements per tile along z).
+// Slot of boundary node (lx, ly, lz) of tile t (local node coordinates in the tile's node
+// box; tz = elements per tile along z) in the tile's face arrays of component c: nodes on an
+// x face (lx = 0 or kLinTX) in the x-face array [side][lz][ly], other nodes on a y face in the
+// y-face array [side][lz][lx], the remaining ones (lz = 0 or tz) in the z-face array
+// [side][ly][lx].  Lanes that handle consecutive nodes along a face then touch consecutive
+// words, in the fused kernel and in the skeleton gather.
 __device__ __forceinline__ size_t lin_slot(int t, int c, int lz, int ly, int lx, int tz) {
-    return (((size_t)t * 3 + c) * (tz + 1) + lz) * ((kLinTY + 1) * (kLinTX + 1)) + ly * (kLinTX + 1) + lx;
+    const size_t base = ((size_t)t * 3 + c) * lin_face_words(tz);
+    if (lx == 0 || lx == kLinTX) return base + ((size_t)(lx == kLinTX) * (tz + 1) + lz) * (kLinTY + 1) + ly;
+    const size_t ofs_y = 2 * (size_t)(tz + 1) * (kLinTY + 1);
+    if (ly == 0 || ly == kLinTY) return base + ofs_y + ((size_t)(ly == kLinTY) * (tz + 1) + lz) * (kLinTX + 1) + lx;
+    const size_t ofs_z = ofs_y + 2 * (size_t)(tz + 1) * (kLinTX + 1);
+    return base + ofs_z + ((size_t)(lz != 0) * (kLinTY + 1) + ly) * (kLinTX + 1) + lx;
 }
 
 // One (qy, qz) column of quadrature points: forward X to the reference gradient
@@ -493,25 +502,26 @@ pa_lin_skeleton_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __re
                        const int TZ, const LinSharedNodes sn, const int add) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int gx, gy, gz;
+    // consecutive lanes take consecutive nodes along the face (y on x planes, x on the others)
     if (t < sn.na) {
-        const int64_t r = t / sn.nxp;
-        gx = kLinTX * (int)(t % sn.nxp + 1);
-        gy = (int)(r % g.Ny);
-        gz = (int)(r / g.Ny);
+        const int64_t r = t / g.Ny;
+        gy = (int)(t % g.Ny);
+        gz = (int)(r % g.Nz);
+        gx = kLinTX * (int)(r / g.Nz + 1);
     } else if (t < sn.na + sn.nb) {
         const int64_t u = t - sn.na;
-        const int64_t r = u / sn.nyp;
         const int nxo = g.Nx - sn.nxp;
-        gy = kLinTY * (int)(u % sn.nyp + 1);
-        gx = off_plane((int)(r % nxo), kLinTX, sn.nxp);
-        gz = (int)(r / nxo);
+        const int64_t r = u / nxo;
+        gx = off_plane((int)(u % nxo), kLinTX, sn.nxp);
+        gz = (int)(r % g.Nz);
+        gy = kLinTY * (int)(r / g.Nz + 1);
     } else if (t < sn.na + sn.nb + sn.nc) {
         const int64_t u = t - sn.na - sn.nb;
-        const int64_t r = u / sn.nzp;
-        const int nxo = g.Nx - sn.nxp;
-        gz = TZ * (int)(u % sn.nzp + 1);
-        gx = off_plane((int)(r % nxo), kLinTX, sn.nxp);
-        gy = off_plane((int)(r / nxo), kLinTY, sn.nyp);
+        const int nxo = g.Nx - sn.nxp, nyo = g.Ny - sn.nyp;
+        const int64_t r = u / nxo;
+        gx = off_plane((int)(u % nxo), kLinTX, sn.nxp);
+        gy = off_plane((int)(r % nyo), kLinTY, sn.nyp);
+        gz = TZ * (int)(r / nyo + 1);
     } else {
         return;
     }

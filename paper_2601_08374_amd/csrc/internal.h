@@ -101,6 +101,14 @@ inline int lin_chunk(const int n[3]) {
     return L;
 }
 
+// Words per tile and component of the linear-element skeleton buffer: the tile's
+// boundary nodes in three face arrays, each contiguous along its face (x faces
+// [2][tz+1][TY+1], y faces [2][tz+1][TX+1], z faces [2][TY+1][TX+1]).
+constexpr int64_t lin_face_words(int tz) {
+    return 2 * (int64_t)(tz + 1) * (kLinTY + 1) + 2 * (int64_t)(tz + 1) * (kLinTX + 1) +
+           2 * (int64_t)(kLinTY + 1) * (kLinTX + 1);
+}
+
 inline int64_t lin_tiles(const int n[3], int tz) {
     return (int64_t)((n[0] + kLinTX - 1) / kLinTX) * ((n[1] + kLinTY - 1) / kLinTY) * ((n[2] + tz - 1) / tz);
 }
@@ -111,7 +119,7 @@ inline int64_t lin_tiles(const int n[3], int tz) {
 inline int64_t skeleton_words(int p, const int n[3], bool lin_kernel = true) {
     if (p == 1 && lin_kernel) {
         const int tz = lin_chunk(n);
-        return lin_tiles(n, tz) * 3 * (kLinTX + 1) * (kLinTY + 1) * (tz + 1);
+        return lin_tiles(n, tz) * 3 * lin_face_words(tz);
     }
     const int64_t NE = (int64_t)n[0] * n[1] * n[2];
     const int64_t D = p + 1;
