@@ -29,6 +29,7 @@ struct LinTabs {
     T B0[Q], B1[Q];   // linear Lagrange basis at the Gauss-Legendre points: 1 - xi_k, xi_k
     T w[Q];           // Gauss-Legendre weights on [0,1]
     T wzy[Q * Q];     // w[qz] * w[qy]
+    T wm[3];          // moments of the rule: sum_k w[k] xi_k^m, m = 0, 1, 2
 };
 
 // 12 words of per-element data with 16-byte loads (the rows are 48 or 96 bytes).
@@ -78,16 +79,19 @@ __device__ __forceinline__ size_t lin_slot(int t, int c, int lz, int ly, int lx,
 // With the linear basis in x, B_x(xi) = (1 - xi, xi) and G_x = (-1, 1), so along the
 // column the reference gradient is linear in xi: g = (a1 - a0, b0 + xi (b1 - b0),
 // e0 + xi (e1 - e0)), and so is the physical gradient, du = D0 + xi D1 (both J^{-T}
-// products formed once per column; du is still evaluated at every point).  On the way
+// products formed once per column).  On the way
 // back, J^{-1} is constant over the element, so the x sums of Q = sigma J^{-T} are
-// J^{-1} applied to the x sums of sigma: the points accumulate the moments
-// M0 = sum w sigma and M1 = sum w xi sigma (6 Voigt entries each), and
+// J^{-1} applied to the x sums of sigma, the moments M0 = sum w sigma and
+// M1 = sum w xi sigma (6 Voigt entries each), and
 // S0 = sum Q_0 = M0 J^{-1}_0, r_m = (sum (1 - xi) Q_m, sum xi Q_m) = ((M0 - M1) J^{-1}_m, M1 J^{-1}_m).
+// With the Lame weights constant along the column the stress is linear in xi as well,
+// sigma = s0 + xi s1 (s0, s1 the stresses of D0 and D1), so the point sums reduce to the
+// rule's moments W_m = sum w xi^m: M0 = W0 s0 + W1 s1, M1 = W1 s0 + W2 s1 (the same sums,
+// regrouped).  Per-point Lame data (QPM) sums the stress point by point.
 template <int Q, typename T, bool QPM = false>
-__device__ __forceinline__ void lin_column(const T (&a)[3][2], const T (&b)[3][2], const T (&e)[3][2],
-                                           const T (&Ji)[9], const T lzy, const T mzy, const LinTabs<T, Q>& tb,
-                                           T (&S0)[3], T (&r1)[3][2], T (&r2)[3][2], const T* lq = nullptr,
-                                           const T* mq = nullptr) {
+__device__ __forceinline__ void lin_moments(const T (&a)[3][2], const T (&b)[3][2], const T (&e)[3][2],
+                                            const T (&Ji)[9], const T lzy, const T mzy, const LinTabs<T, Q>& tb,
+                                            T (&M0)[6], T (&M1)[6], const T* lq = nullptr, const T* mq = nullptr) {
     T D0[3][3], D1[3][3];   // du[c][i] = d u_c / d x_i = D0[c][i] + xi D1[c][i]
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -99,34 +103,59 @@ __device__ __forceinline__ void lin_column(const T (&a)[3][2], const T (&b)[3][2
         }
     }
     // Voigt moments: entries (xx, yy, zz, yz, xz, xy)
-    T M0[6], M1[6];
-#pragma unroll
-    for (int v = 0; v < 6; ++v) M0[v] = M1[v] = T(0);
-#pragma unroll
-    for (int qx = 0; qx < Q; ++qx) {
-        const T xi = tb.B1[qx];
-        const T lam = QPM ? lzy * tb.w[qx] * lq[qx] : lzy * tb.w[qx];
-        const T mu = QPM ? mzy * tb.w[qx] * mq[qx] : mzy * tb.w[qx];
-        T du[3][3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int i = 0; i < 3; ++i) du[c][i] = fma(xi, D1[c][i], D0[c][i]);
-        const T div = du[0][0] + du[1][1] + du[2][2];
-        const T ld = lam * div, m2 = mu + mu;
-        T sv[6];
-        sv[0] = ld + m2 * du[0][0];
-        sv[1] = ld + m2 * du[1][1];
-        sv[2] = ld + m2 * du[2][2];
-        sv[3] = mu * (du[1][2] + du[2][1]);
-        sv[4] = mu * (du[0][2] + du[2][0]);
-        sv[5] = mu * (du[0][1] + du[1][0]);
+    if constexpr (!QPM) {
+        auto voigt = [&](const T (&G)[3][3], T (&sv)[6]) {
+            const T ld = lzy * (G[0][0] + G[1][1] + G[2][2]), m2 = mzy + mzy;
+            sv[0] = ld + m2 * G[0][0];
+            sv[1] = ld + m2 * G[1][1];
+            sv[2] = ld + m2 * G[2][2];
+            sv[3] = mzy * (G[1][2] + G[2][1]);
+            sv[4] = mzy * (G[0][2] + G[2][0]);
+            sv[5] = mzy * (G[0][1] + G[1][0]);
+        };
+        T s0[6], s1[6];
+        voigt(D0, s0);
+        voigt(D1, s1);
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
-            M0[v] += sv[v];
-            M1[v] = fma(xi, sv[v], M1[v]);
+            M0[v] = fma(tb.wm[1], s1[v], tb.wm[0] * s0[v]);
+            M1[v] = fma(tb.wm[2], s1[v], tb.wm[1] * s0[v]);
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < 6; ++v) M0[v] = M1[v] = T(0);
+#pragma unroll
+        for (int qx = 0; qx < Q; ++qx) {
+            const T xi = tb.B1[qx];
+            const T lam = lzy * tb.w[qx] * lq[qx], mu = mzy * tb.w[qx] * mq[qx];
+            T du[3][3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) du[c][i] = fma(xi, D1[c][i], D0[c][i]);
+            const T div = du[0][0] + du[1][1] + du[2][2];
+            const T ld = lam * div, m2 = mu + mu;
+            T sv[6];
+            sv[0] = ld + m2 * du[0][0];
+            sv[1] = ld + m2 * du[1][1];
+            sv[2] = ld + m2 * du[2][2];
+            sv[3] = mu * (du[1][2] + du[2][1]);
+            sv[4] = mu * (du[0][2] + du[2][0]);
+            sv[5] = mu * (du[0][1] + du[1][0]);
+#pragma unroll
+            for (int v = 0; v < 6; ++v) {
+                M0[v] += sv[v];
+                M1[v] = fma(xi, sv[v], M1[v]);
+            }
         }
     }
+}
+
+// The backward X channels from the two Voigt moments: S0 = M0 J^{-1}_0,
+// r_m = ((M0 - M1) J^{-1}_m, M1 J^{-1}_m) for m = 1, 2 (linear in the moments).
+template <typename T>
+__device__ __forceinline__ void lin_project(const T (&M0)[6], const T (&M1)[6], const T (&Ji)[9], T (&S0)[3],
+                                            T (&r1)[3][2], T (&r2)[3][2]) {
     // sigma[c][i] as a Voigt index
     constexpr int kV[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
 #pragma unroll
@@ -147,6 +176,16 @@ __device__ __forceinline__ void lin_column(const T (&a)[3][2], const T (&b)[3][2
         r2[c][0] = R2 - X2;
         r2[c][1] = X2;
     }
+}
+
+template <int Q, typename T, bool QPM = false>
+__device__ __forceinline__ void lin_column(const T (&a)[3][2], const T (&b)[3][2], const T (&e)[3][2],
+                                           const T (&Ji)[9], const T lzy, const T mzy, const LinTabs<T, Q>& tb,
+                                           T (&S0)[3], T (&r1)[3][2], T (&r2)[3][2], const T* lq = nullptr,
+                                           const T* mq = nullptr) {
+    T M0[6], M1[6];
+    lin_moments<Q, T, QPM>(a, b, e, Ji, lzy, mzy, tb, M0, M1, lq, mq);
+    lin_project(M0, M1, Ji, S0, r1, r2);
 }
 
 // Element contribution y_e = K_e x_e of one element with everything in registers,
@@ -236,20 +275,32 @@ __device__ __forceinline__ void lin_element_reg(const T (&xa)[12], const T (&xb)
     }
 }
 
-// The same with the x faces read from the lane's LDS column (stride kLinLds) in
-// every (qz, qy) step and the backward Y/Z sweeps folded straight into the face
-// results: used in double precision, where this keeps the lane's state within
-// 256 VGPRs (two waves per SIMD instead of one).
+// The same with the element's nodal values read from the lane's LDS column (stride
+// kLinLds) in every (qz, qy) step, in a difference form that makes the forward Y/Z
+// interpolation four FMAs per x-column, and the backward Y/Z sweeps folded straight
+// into the face results: used in double precision, where this keeps the lane's state
+// within 256 VGPRs (two waves per SIMD instead of one).
 constexpr int kLinLds = 256;   // lanes per workgroup = LDS column stride
 
 // Compiler barrier: values staged in LDS are re-read after it instead of being
 // kept live in registers.
 __device__ __forceinline__ void lds_reload_point() { __asm__ volatile("" ::: "memory"); }
 
+// Words of a lane's LDS column per element in double precision: the element's nodal values
+// in a difference form (kLinNodeWords) and the lower x face of the next element (12).
+constexpr int kLinNodeWords = 24;
+
+// Nodal values of component c, x-column ix of an element in difference form: with a0, a1
+// the nodes (iy = 0, 1) of the lower face and b0, b1 those of the upper face, the words
+// (a0, a1 - a0, b0 - a0, (b1 - a1) - (b0 - a0)).  Interpolated to (eta, zeta) the node
+// values are then bilinear in these four with unit coefficients: B_z x at iy is
+// a_iy + zeta (b_iy - a_iy), B_y of it is z0 + eta (z1 - z0), and
+// z1 - z0 = (a1 - a0) + zeta ((b1 - a1) - (b0 - a0)).
+__device__ __forceinline__ int lin_node_word(int c, int ix, int w) { return (c * 2 + ix) * 4 + w; }
+
 template <int Q, typename T, bool QPM = false>
-__device__ __forceinline__ void lin_element_lds(const T* __restrict__ xa, const T* __restrict__ xb,
-                                                const T (&d)[12], const LinTabs<T, Q>& tb, T (&ya)[12],
-                                                T (&yb)[12], const T* mdp = nullptr, size_t ns = 0) {
+__device__ __forceinline__ void lin_element_lds(const T* __restrict__ nd, const T (&d)[12], const LinTabs<T, Q>& tb,
+                                                T (&ya)[12], T (&yb)[12], const T* mdp = nullptr, size_t ns = 0) {
     constexpr int S = kLinLds;
     T Ji[9];
 #pragma unroll
@@ -258,42 +309,85 @@ __device__ __forceinline__ void lin_element_lds(const T* __restrict__ xa, const 
 #pragma unroll 1
     for (int qz = 0; qz < Q; ++qz) {
         const T bz0 = tb.B0[qz], bz1 = tb.B1[qz];
+        // sums over the layer's columns of the Voigt moments and eta times them
+        T hM0[6], hM1[6], hE0[6], hE1[6];
+#pragma unroll
+        for (int v = 0; v < 6; ++v) hM0[v] = hM1[v] = hE0[v] = hE1[v] = T(0);
 #pragma unroll 1
         for (int qy = 0; qy < Q; ++qy) {
             lds_reload_point();
-            const T by0 = tb.B0[qy], by1 = tb.B1[qy];
+            const T by1 = tb.B1[qy];
             const T wzy = tb.wzy[qz * Q + qy];
+            // a = B_y B_z x, b = G_y B_z x, e = B_y G_z x at (eta, zeta) = (by1, bz1)
             T a[3][2], b[3][2], e[3][2];
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int ix = 0; ix < 2; ++ix) {
-                    const T a0 = xa[(c * 4 + ix) * S], a1 = xa[(c * 4 + 2 + ix) * S];
-                    const T b0 = xb[(c * 4 + ix) * S], b1 = xb[(c * 4 + 2 + ix) * S];
-                    const T z0 = bz0 * a0 + bz1 * b0, z1 = bz0 * a1 + bz1 * b1;
-                    a[c][ix] = by0 * z0 + by1 * z1;
-                    b[c][ix] = z1 - z0;
-                    e[c][ix] = by0 * (b0 - a0) + by1 * (b1 - a1);
+                    const T n0 = nd[lin_node_word(c, ix, 0) * S], ny = nd[lin_node_word(c, ix, 1) * S];
+                    const T nz = nd[lin_node_word(c, ix, 2) * S], nyz = nd[lin_node_word(c, ix, 3) * S];
+                    const T z0 = fma(bz1, nz, n0);
+                    b[c][ix] = fma(bz1, nyz, ny);
+                    a[c][ix] = fma(by1, b[c][ix], z0);
+                    e[c][ix] = fma(by1, nyz, nz);
                 }
-            T S0[3], r1[3][2], r2[3][2], lq[Q], mq[Q];
+            T M0[6], M1[6], lq[Q], mq[Q];
             lin_point_lame<Q, T, QPM>(mdp, ns, qz, qy, lq, mq);
-            lin_column<Q, T, QPM>(a, b, e, Ji, lw * wzy, mw * wzy, tb, S0, r1, r2, lq, mq);
-            // backward Y and Z into the faces: t0 = B_y (G_x channel) + G_y (channel 1)
-            // takes B_z, t2 = B_y (channel 2) takes G_z = (-1, +1)
+            lin_moments<Q, T, QPM>(a, b, e, Ji, lw * wzy, mw * wzy, tb, M0, M1, lq, mq);
+            if constexpr (QPM) {
+                // backward Y and Z of the column into the faces (the layer sums below would
+                // not leave per-point data two waves per SIMD)
+                T S0[3], r1[3][2], r2[3][2];
+                lin_project(M0, M1, Ji, S0, r1, r2);
+                const T by0 = tb.B0[qy];
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
+                for (int c = 0; c < 3; ++c)
 #pragma unroll
-                for (int iy = 0; iy < 2; ++iy) {
-                    const T by = iy ? by1 : by0;
+                    for (int iy = 0; iy < 2; ++iy) {
+                        const T by = iy ? by1 : by0;
+#pragma unroll
+                        for (int ix = 0; ix < 2; ++ix) {
+                            const int k = c * 4 + iy * 2 + ix;
+                            const T t0 = (ix ? by : -by) * S0[c] + (iy ? r1[c][ix] : -r1[c][ix]);
+                            const T t2 = by * r2[c][ix];
+                            ya[k] += bz0 * t0 - t2;
+                            yb[k] += bz1 * t0 + t2;
+                        }
+                    }
+            } else {
+#pragma unroll
+                for (int v = 0; v < 6; ++v) {
+                    hM0[v] += M0[v];
+                    hM1[v] += M1[v];
+                    hE0[v] = fma(by1, M0[v], hE0[v]);
+                    hE1[v] = fma(by1, M1[v], hE1[v]);
+                }
+            }
+        }
+        if constexpr (!QPM) {
+            // the backward X channels are linear in the moments, so their sums over the
+            // layer (hS = sum S0, hSe = sum eta S0, hr1 = sum r1, hr2 = sum r2,
+            // hr2e = sum eta r2) are the projections of the moment sums
+            T hS[3], hr1[3][2], hr2[3][2], hSe[3], hr1e[3][2], hr2e[3][2];
+            lin_project(hM0, hM1, Ji, hS, hr1, hr2);
+            lin_project(hE0, hE1, Ji, hSe, hr1e, hr2e);
+            // backward Y of the layer (B_y = (1 - eta, eta), G_y = (-1, 1)):
+            // t0 = B_y S0 (sign of G_x by ix) + G_y r1 takes B_z, t2 = B_y r2 takes G_z = (-1, +1)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const T sy0 = hS[c] - hSe[c];
+#pragma unroll
+                for (int iy = 0; iy < 2; ++iy)
 #pragma unroll
                     for (int ix = 0; ix < 2; ++ix) {
                         const int k = c * 4 + iy * 2 + ix;
-                        const T t0 = (ix ? by : -by) * S0[c] + (iy ? r1[c][ix] : -r1[c][ix]);
-                        const T t2 = by * r2[c][ix];
+                        const T sy = iy ? hSe[c] : sy0;
+                        const T t0 = (ix ? sy : -sy) + (iy ? hr1[c][ix] : -hr1[c][ix]);
+                        const T t2 = iy ? hr2e[c][ix] : hr2[c][ix] - hr2e[c][ix];
                         ya[k] += bz0 * t0 - t2;
                         yb[k] += bz1 * t0 + t2;
                     }
-                }
+            }
         }
     }
 }
@@ -398,30 +492,42 @@ pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ 
 #pragma unroll
     for (int k = 0; k < 12; ++k) ya[k] = T(0);
     if constexpr (kLinXInLds<T>) {
-        // x faces in two alternating LDS buffers; the next element's data is loaded
-        // after the current element (two waves per SIMD hide the latency)
-        __shared__ T s_x[24 * kLinLds];
+        // the element's nodal values in difference form and the lower x face of the next
+        // element in the lane's LDS column; the next element's data is loaded after the
+        // current element (two waves per SIMD hide the latency)
+        __shared__ T s_x[(kLinNodeWords + 12) * kLinLds];
         T* const col = s_x + threadIdx.x;
-        auto store_face = [&](int buf, const T (&f)[12]) {
+        T* const face = col + kLinNodeWords * kLinLds;
+        auto store_face = [&](const T (&f)[12]) {
 #pragma unroll
-            for (int k = 0; k < 12; ++k) col[(12 * buf + k) * kLinLds] = f[k];
+            for (int k = 0; k < 12; ++k) face[k * kLinLds] = f[k];
         };
         load_face(ez0, xn);
-        store_face(0, xn);
+        store_face(xn);
         load_face(ez0 + 1, xn);
         load_data(ez0, dn);
-        int fa = 0;
 #pragma unroll 1
         for (int ez = ez0; ez < ez1; ++ez) {
             T d[12], yb[12];
-            store_face(1 - fa, xn);
+            // lower face from LDS, upper face (xn) from registers
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int ix = 0; ix < 2; ++ix) {
+                    const T a0 = face[(c * 4 + ix) * kLinLds], a1 = face[(c * 4 + 2 + ix) * kLinLds];
+                    const T dz = xn[c * 4 + ix] - a0;
+                    col[lin_node_word(c, ix, 0) * kLinLds] = a0;
+                    col[lin_node_word(c, ix, 1) * kLinLds] = a1 - a0;
+                    col[lin_node_word(c, ix, 2) * kLinLds] = dz;
+                    col[lin_node_word(c, ix, 3) * kLinLds] = (xn[c * 4 + 2 + ix] - a1) - dz;
+                }
+            store_face(xn);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 d[k] = dn[k];
                 yb[k] = T(0);
             }
-            lin_element_lds<Q, T, QPM>(col + 12 * fa * kLinLds, col + 12 * (1 - fa) * kLinLds, d, tb, ya, yb,
-                                       mat_ptr(ez), (size_t)g.NE);
+            lin_element_lds<Q, T, QPM>(col, d, tb, ya, yb, mat_ptr(ez), (size_t)g.NE);
             if (ez + 1 < ez1) {
                 load_face(ez + 2, xn);
                 load_data(ez + 1, dn);
@@ -431,7 +537,6 @@ pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ 
             emit_layer(v, ez);
 #pragma unroll
             for (int k = 0; k < 12; ++k) ya[k] = yb[k];
-            fa ^= 1;
         }
     } else {
         // everything in registers; the next element's data is prefetched
@@ -589,6 +694,11 @@ int launch_lin(const ApplyLaunch& L) {
         tb.B0[k] = (T)L.tab->B[0 * Q + k];
         tb.B1[k] = (T)L.tab->B[1 * Q + k];
         tb.w[k] = (T)L.tab->w[k];
+    }
+    for (int m = 0; m < 3; ++m) {
+        double acc = 0.0;
+        for (int k = 0; k < Q; ++k) acc += L.tab->w[k] * (m == 0 ? 1.0 : m == 1 ? L.tab->B[Q + k] : L.tab->B[Q + k] * L.tab->B[Q + k]);
+        tb.wm[m] = (T)acc;
     }
     for (int qz = 0; qz < Q; ++qz)
         for (int qy = 0; qy < Q; ++qy) tb.wzy[qz * Q + qy] = (T)(L.tab->w[qz] * L.tab->w[qy]);
