@@ -178,20 +178,6 @@ __device__ __forceinline__ void lin_project(const T (&M0)[6], const T (&M1)[6], 
     }
 }
 
-template <int Q, typename T, bool QPM = false>
-__device__ __forceinline__ void lin_column(const T (&a)[3][2], const T (&b)[3][2], const T (&e)[3][2],
-                                           const T (&Ji)[9], const T lzy, const T mzy, const LinTabs<T, Q>& tb,
-                                           T (&S0)[3], T (&r1)[3][2], T (&r2)[3][2], const T* lq = nullptr,
-                                           const T* mq = nullptr) {
-    T M0[6], M1[6];
-    lin_moments<Q, T, QPM>(a, b, e, Ji, lzy, mzy, tb, M0, M1, lq, mq);
-    lin_project(M0, M1, Ji, S0, r1, r2);
-}
-
-// Element contribution y_e = K_e x_e of one element with everything in registers,
-// added to ya (lower face iz = 0) and yb (upper face iz = 1); word k of a face is
-// (c, iy, ix) = (k >> 2, (k >> 1) & 1, k & 1).  Used in single precision, where
-// the lane's state fits two waves per SIMD.
 // Per-point material (QPM): mdp points at the element's (lambda, mu) of point 0; point
 // alpha, word k is mdp[(2 alpha + k) * ns] (point-major layout, elements contiguous).
 template <int Q, typename T, bool QPM>
@@ -206,89 +192,11 @@ __device__ __forceinline__ void lin_point_lame(const T* mdp, size_t ns, int qz, 
     }
 }
 
-template <int Q, typename T, bool QPM = false>
-__device__ __forceinline__ void lin_element_reg(const T (&xa)[12], const T (&xb)[12], const T (&d)[12],
-                                                const LinTabs<T, Q>& tb, T (&ya)[12], T (&yb)[12],
-                                                const T* mdp = nullptr, size_t ns = 0) {
-    T Ji[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) Ji[k] = d[k];
-    const T lw = d[9], mw = d[10];
-    T dz[12], U2[12];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-        dz[k] = xb[k] - xa[k];
-        U2[k] = T(0);
-    }
-#pragma unroll 1
-    for (int qz = 0; qz < Q; ++qz) {
-        const T bz0 = tb.B0[qz], bz1 = tb.B1[qz];
-        T xz[12], t0[12], t2[12];
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            xz[k] = bz0 * xa[k] + bz1 * xb[k];
-            t0[k] = t2[k] = T(0);
-        }
-#pragma unroll 1
-        for (int qy = 0; qy < Q; ++qy) {
-            const T by0 = tb.B0[qy], by1 = tb.B1[qy];
-            const T wzy = tb.wzy[qz * Q + qy];
-            T a[3][2], b[3][2], e[3][2];
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int ix = 0; ix < 2; ++ix) {
-                    const T z0 = xz[c * 4 + ix], z1 = xz[c * 4 + 2 + ix];
-                    a[c][ix] = by0 * z0 + by1 * z1;
-                    b[c][ix] = z1 - z0;
-                    e[c][ix] = by0 * dz[c * 4 + ix] + by1 * dz[c * 4 + 2 + ix];
-                }
-            T S0[3], r1[3][2], r2[3][2], lq[Q], mq[Q];
-            lin_point_lame<Q, T, QPM>(mdp, ns, qz, qy, lq, mq);
-            lin_column<Q, T, QPM>(a, b, e, Ji, lw * wzy, mw * wzy, tb, S0, r1, r2, lq, mq);
-            // backward Y: t0 += B_y (G_x channel) + G_y (channel 1), t2 += B_y (channel 2)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int iy = 0; iy < 2; ++iy) {
-                    const T by = iy ? by1 : by0;
-#pragma unroll
-                    for (int ix = 0; ix < 2; ++ix) {
-                        const int k = c * 4 + iy * 2 + ix;
-                        t0[k] += (ix ? by : -by) * S0[c] + (iy ? r1[c][ix] : -r1[c][ix]);
-                        t2[k] += by * r2[c][ix];
-                    }
-                }
-        }
-        // backward Z: B_z for channels 0 and 1; the G_z channel is summed over qz first
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            ya[k] += bz0 * t0[k];
-            yb[k] += bz1 * t0[k];
-            U2[k] += t2[k];
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-        ya[k] -= U2[k];
-        yb[k] += U2[k];
-    }
-}
-
-// The same with the element's nodal values read from the lane's LDS column (stride
-// kLinLds) in every (qz, qy) step, in a difference form that makes the forward Y/Z
-// interpolation four FMAs per x-column, and the backward Y/Z sweeps folded straight
-// into the face results: used in double precision, where this keeps the lane's state
-// within 256 VGPRs (two waves per SIMD instead of one).
 constexpr int kLinLds = 256;   // lanes per workgroup = LDS column stride
 
 // Compiler barrier: values staged in LDS are re-read after it instead of being
 // kept live in registers.
 __device__ __forceinline__ void lds_reload_point() { __asm__ volatile("" ::: "memory"); }
-
-// Words of a lane's LDS column per element in double precision: the element's nodal values
-// in a difference form (kLinNodeWords) and the lower x face of the next element (12).
-constexpr int kLinNodeWords = 24;
 
 // Nodal values of component c, x-column ix of an element in difference form: with a0, a1
 // the nodes (iy = 0, 1) of the lower face and b0, b1 those of the upper face, the words
@@ -296,12 +204,51 @@ constexpr int kLinNodeWords = 24;
 // values are then bilinear in these four with unit coefficients: B_z x at iy is
 // a_iy + zeta (b_iy - a_iy), B_y of it is z0 + eta (z1 - z0), and
 // z1 - z0 = (a1 - a0) + zeta ((b1 - a1) - (b0 - a0)).
+constexpr int kLinNodeWords = 24;
 __device__ __forceinline__ int lin_node_word(int c, int ix, int w) { return (c * 2 + ix) * 4 + w; }
 
-template <int Q, typename T, bool QPM = false>
-__device__ __forceinline__ void lin_element_lds(const T* __restrict__ nd, const T (&d)[12], const LinTabs<T, Q>& tb,
-                                                T (&ya)[12], T (&yb)[12], const T* mdp = nullptr, size_t ns = 0) {
-    constexpr int S = kLinLds;
+// the difference form of the element with lower x face fa and upper x face fb (word k of a
+// face is (c, iy, ix) = (k >> 2, (k >> 1) & 1, k & 1)), handed to put(word, value)
+template <typename T, typename F>
+__device__ __forceinline__ void lin_node_form(const T (&fa)[12], const T (&fb)[12], F&& put) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int ix = 0; ix < 2; ++ix) {
+            const T a0 = fa[c * 4 + ix], a1 = fa[c * 4 + 2 + ix];
+            const T dz = fb[c * 4 + ix] - a0;
+            put(lin_node_word(c, ix, 0), a0);
+            put(lin_node_word(c, ix, 1), a1 - a0);
+            put(lin_node_word(c, ix, 2), dz);
+            put(lin_node_word(c, ix, 3), (fb[c * 4 + 2 + ix] - a1) - dz);
+        }
+}
+
+// where an element's difference form is read from: the lane's LDS column (double
+// precision, re-read in every column so that it does not hold registers) or registers
+struct LinNodesLds {
+    static constexpr bool kLds = true;
+    static constexpr int kStride = kLinLds;
+};
+struct LinNodesReg {
+    static constexpr bool kLds = false;
+    static constexpr int kStride = 1;
+};
+
+// Element contribution y_e = K_e x_e of one element, added to ya (lower face iz = 0) and
+// yb (upper face iz = 1); word k of a face is (c, iy, ix) = (k >> 2, (k >> 1) & 1, k & 1).
+// nd holds the element's nodal values in difference form (word w at nd[w * Src::kStride]).
+// Per (qz, qy) column: the forward Y/Z interpolation (four FMAs per x-column), the
+// column's Voigt moments (lin_moments).  With per-element Lame weights the backward X
+// channels are linear in the moments, so a z layer sums the moments of its columns and
+// eta times them, and projects the sums once (the layer sums of S0, eta S0, r1, r2 and
+// eta r2), then runs the backward Y sweep (B_y = (1 - eta, eta), G_y = (-1, 1)) and the
+// backward Z sweep into the faces.  Per-point material (QPM) projects every column and
+// sweeps it back by itself.
+template <int Q, typename T, bool QPM, typename Src>
+__device__ __forceinline__ void lin_element(const T* nd, const T (&d)[12], const LinTabs<T, Q>& tb,
+                                            T (&ya)[12], T (&yb)[12], const T* mdp = nullptr, size_t ns = 0) {
+    constexpr int stride = Src::kStride;
     T Ji[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) Ji[k] = d[k];
@@ -315,7 +262,7 @@ __device__ __forceinline__ void lin_element_lds(const T* __restrict__ nd, const 
         for (int v = 0; v < 6; ++v) hM0[v] = hM1[v] = hE0[v] = hE1[v] = T(0);
 #pragma unroll 1
         for (int qy = 0; qy < Q; ++qy) {
-            lds_reload_point();
+            if constexpr (Src::kLds) lds_reload_point();
             const T by1 = tb.B1[qy];
             const T wzy = tb.wzy[qz * Q + qy];
             // a = B_y B_z x, b = G_y B_z x, e = B_y G_z x at (eta, zeta) = (by1, bz1)
@@ -324,8 +271,8 @@ __device__ __forceinline__ void lin_element_lds(const T* __restrict__ nd, const 
             for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int ix = 0; ix < 2; ++ix) {
-                    const T n0 = nd[lin_node_word(c, ix, 0) * S], ny = nd[lin_node_word(c, ix, 1) * S];
-                    const T nz = nd[lin_node_word(c, ix, 2) * S], nyz = nd[lin_node_word(c, ix, 3) * S];
+                    const T n0 = nd[lin_node_word(c, ix, 0) * stride], ny = nd[lin_node_word(c, ix, 1) * stride];
+                    const T nz = nd[lin_node_word(c, ix, 2) * stride], nyz = nd[lin_node_word(c, ix, 3) * stride];
                     const T z0 = fma(bz1, nz, n0);
                     b[c][ix] = fma(bz1, nyz, ny);
                     a[c][ix] = fma(by1, b[c][ix], z0);
@@ -335,8 +282,7 @@ __device__ __forceinline__ void lin_element_lds(const T* __restrict__ nd, const 
             lin_point_lame<Q, T, QPM>(mdp, ns, qz, qy, lq, mq);
             lin_moments<Q, T, QPM>(a, b, e, Ji, lw * wzy, mw * wzy, tb, M0, M1, lq, mq);
             if constexpr (QPM) {
-                // backward Y and Z of the column into the faces (the layer sums below would
-                // not leave per-point data two waves per SIMD)
+                // t0 = B_y S0 (sign of G_x by ix) + G_y r1 takes B_z, t2 = B_y r2 takes G_z = (-1, +1)
                 T S0[3], r1[3][2], r2[3][2];
                 lin_project(M0, M1, Ji, S0, r1, r2);
                 const T by0 = tb.B0[qy];
@@ -365,14 +311,9 @@ __device__ __forceinline__ void lin_element_lds(const T* __restrict__ nd, const 
             }
         }
         if constexpr (!QPM) {
-            // the backward X channels are linear in the moments, so their sums over the
-            // layer (hS = sum S0, hSe = sum eta S0, hr1 = sum r1, hr2 = sum r2,
-            // hr2e = sum eta r2) are the projections of the moment sums
             T hS[3], hr1[3][2], hr2[3][2], hSe[3], hr1e[3][2], hr2e[3][2];
             lin_project(hM0, hM1, Ji, hS, hr1, hr2);
             lin_project(hE0, hE1, Ji, hSe, hr1e, hr2e);
-            // backward Y of the layer (B_y = (1 - eta, eta), G_y = (-1, 1)):
-            // t0 = B_y S0 (sign of G_x by ix) + G_y r1 takes B_z, t2 = B_y r2 takes G_z = (-1, +1)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const T sy0 = hS[c] - hSe[c];
@@ -510,24 +451,17 @@ pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ 
         for (int ez = ez0; ez < ez1; ++ez) {
             T d[12], yb[12];
             // lower face from LDS, upper face (xn) from registers
+            T fl[12];
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int ix = 0; ix < 2; ++ix) {
-                    const T a0 = face[(c * 4 + ix) * kLinLds], a1 = face[(c * 4 + 2 + ix) * kLinLds];
-                    const T dz = xn[c * 4 + ix] - a0;
-                    col[lin_node_word(c, ix, 0) * kLinLds] = a0;
-                    col[lin_node_word(c, ix, 1) * kLinLds] = a1 - a0;
-                    col[lin_node_word(c, ix, 2) * kLinLds] = dz;
-                    col[lin_node_word(c, ix, 3) * kLinLds] = (xn[c * 4 + 2 + ix] - a1) - dz;
-                }
+            for (int k = 0; k < 12; ++k) fl[k] = face[k * kLinLds];
+            lin_node_form(fl, xn, [&](int w, T v) { col[w * kLinLds] = v; });
             store_face(xn);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 d[k] = dn[k];
                 yb[k] = T(0);
             }
-            lin_element_lds<Q, T, QPM>(col, d, tb, ya, yb, mat_ptr(ez), (size_t)g.NE);
+            lin_element<Q, T, QPM, LinNodesLds>(col, d, tb, ya, yb, mat_ptr(ez), (size_t)g.NE);
             if (ez + 1 < ez1) {
                 load_face(ez + 2, xn);
                 load_data(ez + 1, dn);
@@ -557,7 +491,9 @@ pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ 
                 load_face(ez + 2, xn);
                 load_data(ez + 1, dn);
             }
-            lin_element_reg<Q, T, QPM>(xa, xb, d, tb, ya, yb, mat_ptr(ez), (size_t)g.NE);
+            T nd[kLinNodeWords];
+            lin_node_form(xa, xb, [&](int w, T v) { nd[w] = v; });
+            lin_element<Q, T, QPM, LinNodesReg>(nd, d, tb, ya, yb, mat_ptr(ez), (size_t)g.NE);
             T v[3][2][2];
             to_face(ya, v);
             emit_layer(v, ez);
