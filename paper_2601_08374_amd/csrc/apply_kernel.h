@@ -290,6 +290,10 @@ struct Skel {
     __device__ __forceinline__ static size_t offset(int e, int c, int s, int NE) {
         return ELEM_MAJOR ? ((size_t)e * 3 + c) * S + s : ((size_t)c * S + s) * NE + e;
     }
+    // offset(e, c, s, NE) - offset(e, c, 0, NE)
+    __device__ __forceinline__ static size_t slot_offset(int s, int NE) {
+        return ELEM_MAJOR ? (size_t)s : (size_t)(unsigned)s * (unsigned)NE;
+    }
 };
 
 // LDS layout of one element: Ua[ch][iz][iy][qx] (X-pass output, two channels;
@@ -442,6 +446,8 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
     static_assert(GX * D <= 32, "clamp mask bits");
     int ln_node[GX];       // global node of (ix = 0) of the line (unstructured: 0, KL: its word in Ks), or -1
     int ln_slot[GX];       // skeleton slot of (ix = 0) of the line
+    int ln_el[GX];         // element of the line in the block
+    int ln_ua[GX];         // word of the line's (qx = 0) in Ua
     unsigned ln_full = 0u; // bit j: the line lies on the element boundary
     unsigned ln_cl = 0u;   // bit j*D + ix: clamped node (read as 0)
     int ln_nodes[UNS && !KL ? GX : 1][UNS && !KL ? D : 1];   // unstructured: every node of the line
@@ -450,6 +456,8 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
         if constexpr (KL) return (unsigned)Ks[ln_node[j] + ix] & ~kClampBit;
         else return (size_t)ln_nodes[UNS ? j : 0][UNS ? ix : 0];
     };
+    // box coordinates of the block's first element (block-uniform)
+    const int bx0 = e0 % g.nx, bxr = e0 / g.nx, by0 = bxr % g.ny, bz0 = bxr / g.ny;
     // the lines' node addresses and clamp flags come from the element numbers (from the
     // block's map in LDS when KL), so that the first x loads are in flight while the
     // element data is staged
@@ -458,11 +466,15 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
     for (int j = 0; j < GX; ++j) {
         ln_node[j] = -1;
         ln_slot[j] = 0;
+        ln_el[j] = 0;
+        ln_ua[j] = 0;
         const int l = tid + j * NT;
         if (l < NL) {
             const int el = l / (D * D), r = l % (D * D);
             const int iz = r / D, iy = r % D;
             const bool valid = el < ne_blk;
+            ln_el[j] = el;
+            ln_ua[j] = el * UT + iz * UZ + iy * UY;
             ln_slot[j] = SK::index(0, iy, iz);
             if (SK::full_row(iy, iz)) ln_full |= 1u << j;
             if (KL && valid) {
@@ -482,9 +494,16 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
                     if (g.clamp && (v & kClampBit)) ln_cl |= 1u << (j * D + ix);
                 }
             } else if (valid) {
-                const int e = e0 + el;
-                const int ex = e % g.nx, er = e / g.nx;
-                const int gx0 = ex * P, gy0 = (er % g.ny) * P, gz0 = (er / g.ny) * P;
+                // element e0 + el: step from the block's first element (no per-lane division)
+                int ex = bx0 + el, ey = by0, ez = bz0;
+                while (ex >= g.nx) {
+                    ex -= g.nx;
+                    if (++ey == g.ny) {
+                        ey = 0;
+                        ++ez;
+                    }
+                }
+                const int gx0 = ex * P, gy0 = ey * P, gz0 = ez * P;
                 ln_node[j] = gx0 + g.Nx * (gy0 + iy + g.Ny * (gz0 + iz));
                 if (g.clamp) {
 #pragma unroll
@@ -529,6 +548,26 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
         line_load(0);
     }
 
+    // Y-pass line (el, iz, qx) of word w: its offsets in Ua and Ra; when one pass of the
+    // workgroup covers all lines, the thread's line is computed once for every sweep
+    constexpr bool Y1 = E * D * Q <= NT;
+    auto yline = [&](int w, int& ua, int& ra) {
+        const int el = w / (D * Q), r = w % (D * Q);
+        const int iz = r / Q, qx = r % Q;
+        ua = el * UT + iz * UZ + qx;
+        ra = el * ST + iz * RZ + qx;
+    };
+    int y1_ua = 0, y1_ra = 0;
+    if constexpr (Y1) yline(tid, y1_ua, y1_ra);
+    auto yoffs = [&](int w, int& ua, int& ra) {
+        if constexpr (Y1) {
+            ua = y1_ua;
+            ra = y1_ra;
+        } else {
+            yline(w, ua, ra);
+        }
+    };
+
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         // ---- forward X from the x lines: Ua[el][ch][iz][iy][qx]
@@ -536,11 +575,10 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
         for (int j = 0; j < GX; ++j) {
             const int l = tid + j * NT;
             if (l < NL) {
-                const int el = l / (D * D), r = l % (D * D);
                 T u[Q], v[Q];
                 eo_contract<1, false>(xr[j], u, tab.Bf);
                 eo_contract<-1, false>(xr[j], v, tab.Gf);
-                T* uo = Ua + el * UT + (r / D) * UZ + (r % D) * UY;
+                T* uo = Ua + ln_ua[j];
 #pragma unroll
                 for (int k = 0; k < Q; ++k) {
                     uo[k] = u[k];
@@ -552,16 +590,16 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
         __syncthreads();
         // ---- forward Y: lines (el, iz, qx): s0 = v B (d/dxi), s1 = u G (d/deta), s2 = u B
         for (int w = tid; w < E * D * Q; w += NT) {
-            const int el = w / (D * Q), r = w % (D * Q);
-            const int iz = r / Q, qx = r % Q;
-            const T* ui = Ua + el * UT + iz * UZ + qx;
+            int ua, ra;
+            yoffs(w, ua, ra);
+            const T* ui = Ua + ua;
             T uv[D], vv[D], s0[Q], s1[Q], s2[Q];
 #pragma unroll
             for (int i = 0; i < D; ++i) { uv[i] = ui[i * UY]; vv[i] = ui[UC + i * UY]; }
             eo_contract<1, false>(vv, s0, tab.Bf);
             eo_contract<-1, false>(uv, s1, tab.Gf);
             eo_contract<1, false>(uv, s2, tab.Bf);
-            T* so = Ra + el * ST + iz * RZ + qx;
+            T* so = Ra + ra;
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
                 so[k * RY] = s0[k];
@@ -721,9 +759,9 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
         __syncthreads();
         // backward Y: lines (el, iz, qx): R0 = T0 B^T, R12 = T1 G^T + T2 B^T
         for (int w = tid; w < E * D * Q; w += NT) {
-            const int el = w / (D * Q), r = w % (D * Q);
-            const int iz = r / Q, qx = r % Q;
-            const T* ti = Ra + el * ST + iz * RZ + qx;
+            int ua, ra;
+            yoffs(w, ua, ra);
+            const T* ti = Ra + ra;
             T a0[Q], a1[Q], a2[Q], r0[D], r12[D];
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
@@ -734,7 +772,7 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
             eo_contract<1, false>(a0, r0, back_B(tab));
             eo_contract<-1, false>(a1, r12, back_G(tab));
             eo_contract<1, true>(a2, r12, back_B(tab));
-            T* ro = Ua + el * UT + iz * UZ + qx;
+            T* ro = Ua + ua;
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 ro[i * UY] = r0[i];
@@ -748,15 +786,15 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
         for (int j = 0; j < GX; ++j) {
             const int l = tid + j * NT;
             if (l < NL && ln_node[j] >= 0) {
-                const int el = l / (D * D), r = l % (D * D);
-                const int iz = r / D, iy = r % D;
-                const T* ri = Ua + el * UT + iz * UZ + iy * UY;
+                const int el = ln_el[j];
+                const T* ri = Ua + ln_ua[j];
                 T a0[Q], a1[Q], yo[D];
 #pragma unroll
                 for (int k = 0; k < Q; ++k) { a0[k] = ri[k]; a1[k] = ri[UC + k]; }
                 eo_contract<-1, false>(a0, yo, back_G(tab));
                 eo_contract<1, true>(a1, yo, back_B(tab));
                 const bool full = (ln_full >> j) & 1u;
+                T* const skl = sk + SK::offset(e0 + el, c, 0, g.NE);   // slot 0 of (element, c)
 #pragma unroll
                 for (int ix = 0; ix < D; ++ix) {
                     // the end nodes of a row are always skeleton nodes
@@ -775,7 +813,7 @@ pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, 
                         T* yp = y + c * NN + ln_node[j] + ix;
                         *yp = add ? *yp + yo[ix] : yo[ix];
                     } else {
-                        sk[SK::offset(e0 + el, c, SK::row_slot(ln_slot[j], full, ix), g.NE)] = yo[ix];
+                        skl[SK::slot_offset(SK::row_slot(ln_slot[j], full, ix), g.NE)] = yo[ix];
                     }
                 }
             }
