@@ -70,8 +70,9 @@ __device__ __forceinline__ size_t lin_slot(int t, int c, int lz, int ly, int lx,
 }
 
 // One (qy, qz) column of quadrature points: forward X to the reference gradient
-// g[c][m], pointwise stress and Q = sigma J^{-T} (weights w[qx] * lzy, mzy), and
-// backward X into S0 (G_x channel, summed over qx) and r1, r2 (B_x channels).
+// g[c][m], pointwise stress (weights w[qx] * lzy, mzy) and its two Voigt moments along the
+// column, from which lin_project forms the backward X channels of Q = sigma J^{-T}: S0
+// (G_x channel, summed over qx) and r1, r2 (B_x channels).
 // Inputs per component c and x-column ix: a = B_y B_z x, b = G_y B_z x, e = B_y G_z x.
 // QPM: per-point Lame parameters lq[qx], mq[qx] of the column scale lzy, mzy (which then
 // carry w det J only).
@@ -510,12 +511,15 @@ pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ 
 }
 
 // The nodes that more than one tile holds (on an interior tile plane x = 8k, y = 8k or
-// z = TZ k), numbered as three sets so that only they get lanes: (a) every node of the
-// interior x planes, (b) the nodes of the interior y planes off the x planes, (c) the nodes
-// of the interior z planes off the x and y planes.
+// z = TZ k), as three sets: (a) every node of the interior x planes, (b) the nodes of the
+// interior y planes off the x planes, (c) the nodes of the interior z planes off the x and
+// y planes.  Each plane is cut into blocks of 8 x 8 nodes, one wavefront per block, so that
+// the lanes of a wavefront read runs of 8 consecutive words in 8 consecutive rows of a
+// tile's face array (lanes of a block past the mesh, or on a plane of an earlier set, idle).
 struct LinSharedNodes {
     int nxp, nyp, nzp;    // interior tile planes along x, y, z
-    int64_t na, nb, nc;   // nodes in each set
+    int bx, by, bz;       // 8-node blocks along x, y, z
+    int64_t la, lb, lc;   // lanes of each set (64 per block)
 };
 
 inline LinSharedNodes lin_shared_nodes(const Geom& g, int TZ) {
@@ -523,16 +527,13 @@ inline LinSharedNodes lin_shared_nodes(const Geom& g, int TZ) {
     s.nxp = (g.nx + kLinTX - 1) / kLinTX - 1;
     s.nyp = (g.ny + kLinTY - 1) / kLinTY - 1;
     s.nzp = (g.nz + TZ - 1) / TZ - 1;
-    s.na = (int64_t)s.nxp * g.Ny * g.Nz;
-    s.nb = (int64_t)s.nyp * (g.Nx - s.nxp) * g.Nz;
-    s.nc = (int64_t)s.nzp * (g.Nx - s.nxp) * (g.Ny - s.nyp);
+    s.bx = (g.Nx + 7) / 8;
+    s.by = (g.Ny + 7) / 8;
+    s.bz = (g.Nz + 7) / 8;
+    s.la = (int64_t)s.nxp * s.by * s.bz * 64;
+    s.lb = (int64_t)s.nyp * s.bx * s.bz * 64;
+    s.lc = (int64_t)s.nzp * s.bx * s.by * 64;
     return s;
-}
-
-// j-th coordinate along an axis that is not on one of the np interior planes at multiples
-// of w (w coordinates before the first plane, w - 1 between two planes)
-__device__ __forceinline__ int off_plane(int j, int w, int np) {
-    return j < w ? j : j + min(np, 1 + (j - w) / (w - 1));
 }
 
 // For every shared tile-boundary node: sum the partial sums of the tiles touching it
@@ -541,28 +542,39 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 pa_lin_skeleton_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ sk, const Geom g,
                        const int TZ, const LinSharedNodes sn, const int add) {
+    static_assert(kLinTX == 8 && kLinTY == 8, "node blocks and tile planes share the 8-node spacing");
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // lane (i, j) of an 8 x 8 node block: i along the block's first axis, j along its second
+    const int i = (int)(t & 7), j = (int)((t >> 3) & 7);
     int gx, gy, gz;
-    // consecutive lanes take consecutive nodes along the face (y on x planes, x on the others)
-    if (t < sn.na) {
-        const int64_t r = t / g.Ny;
-        gy = (int)(t % g.Ny);
-        gz = (int)(r % g.Nz);
-        gx = kLinTX * (int)(r / g.Nz + 1);
-    } else if (t < sn.na + sn.nb) {
-        const int64_t u = t - sn.na;
-        const int nxo = g.Nx - sn.nxp;
-        const int64_t r = u / nxo;
-        gx = off_plane((int)(u % nxo), kLinTX, sn.nxp);
-        gz = (int)(r % g.Nz);
-        gy = kLinTY * (int)(r / g.Nz + 1);
-    } else if (t < sn.na + sn.nb + sn.nc) {
-        const int64_t u = t - sn.na - sn.nb;
-        const int nxo = g.Nx - sn.nxp, nyo = g.Ny - sn.nyp;
-        const int64_t r = u / nxo;
-        gx = off_plane((int)(u % nxo), kLinTX, sn.nxp);
-        gy = off_plane((int)(r % nyo), kLinTY, sn.nyp);
-        gz = TZ * (int)(r / nyo + 1);
+    if (t < sn.la) {
+        // x plane: blocks over (y, z)
+        const int b = (int)(t >> 6);
+        const int r = b / sn.by;
+        gy = 8 * (b % sn.by) + i;
+        gz = 8 * (r % sn.bz) + j;
+        gx = kLinTX * (r / sn.bz + 1);
+        if (gy >= g.Ny || gz >= g.Nz) return;
+    } else if (t < sn.la + sn.lb) {
+        // y plane: blocks over (x, z), nodes on an x plane excluded
+        const int b = (int)((t - sn.la) >> 6);
+        const int r = b / sn.bx;
+        const int bxi = b % sn.bx;
+        gx = 8 * bxi + i;
+        gz = 8 * (r % sn.bz) + j;
+        gy = kLinTY * (r / sn.bz + 1);
+        if (gx >= g.Nx || gz >= g.Nz || (i == 0 && bxi >= 1 && bxi <= sn.nxp)) return;
+    } else if (t < sn.la + sn.lb + sn.lc) {
+        // z plane: blocks over (x, y), nodes on an x or y plane excluded
+        const int b = (int)((t - sn.la - sn.lb) >> 6);
+        const int r = b / sn.bx;
+        const int bxi = b % sn.bx, byi = r % sn.by;
+        gx = 8 * bxi + i;
+        gy = 8 * byi + j;
+        gz = TZ * (r / sn.by + 1);
+        if (gx >= g.Nx || gy >= g.Ny || (i == 0 && bxi >= 1 && bxi <= sn.nxp) ||
+            (j == 0 && byi >= 1 && byi <= sn.nyp))
+            return;
     } else {
         return;
     }
@@ -646,7 +658,7 @@ int launch_lin(const ApplyLaunch& L) {
                        (T*)L.sk, (const T*)L.ed, tb, g, tz, L.add, (const T*)L.md);
     PA_HIP(hipGetLastError());
     const LinSharedNodes sn = lin_shared_nodes(g, tz);
-    const int64_t nsh = sn.na + sn.nb + sn.nc;
+    const int64_t nsh = sn.la + sn.lb + sn.lc;
     if (nsh > 0) {
         hipLaunchKernelGGL((pa_lin_skeleton_kernel<T>), dim3((unsigned)((nsh + 255) / 256)), dim3(256), 0, L.stream,
                            (const T*)L.x, (T*)L.y, (const T*)L.sk, g, tz, sn, L.add);
