@@ -43,10 +43,10 @@ STEP_PS = (1, 2, 4, 6, 8)
 # source hash of the kernels they were taken on, so an edited kernel reports
 # null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("bfd22ca63e3df1b8", 1, "f64"): 303234957,
-    ("bfd22ca63e3df1b8", 2, "f64"): 315951635,
-    ("bfd22ca63e3df1b8", 4, "f64"): 197834374,
-    ("bfd22ca63e3df1b8", 8, "f64"): 138036734,
+    ("e1386668af0eeb51", 1, "f64"): 290352842,
+    ("e1386668af0eeb51", 2, "f64"): 315875817,
+    ("e1386668af0eeb51", 4, "f64"): 197906912,
+    ("e1386668af0eeb51", 8, "f64"): 138013700,
 }
 
 
