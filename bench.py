@@ -26,6 +26,7 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -322,7 +323,7 @@ def main(argv=None):
     ap.add_argument("--solve-mode", choices=("f64", "f32_ir", "f32_prec"), default="f64")
     ap.add_argument("--dtype", choices=("f64", "f32"), default="f64")
     ap.add_argument("--reps", type=int, default=10)
-    ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
+    ap.add_argument("--detail", default=os.path.join(tempfile.gettempdir(), "paelast_bench_detail.json"),
                     help="file for the full results (the stdout line is a summary); empty: none")
     args = ap.parse_args(argv)
 

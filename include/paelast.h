@@ -312,8 +312,8 @@ int gmg_vcycle(pa_gmg_t* g, const void* r, void* z);
  * Returns PA_OK, PA_ENOCONV or PA_EBREAKDOWN; info may be NULL. */
 int gmg_pcg_run(pa_gmg_t* g, const double* b, double* x, double rtol, pa_solve_info_t* info);
 
-/* North-star form: builds (and caches on op) the hierarchy for opts o (NULL:
- * defaults), then runs gmg_pcg_run. */
+/* One-call solve on an operator: builds (and caches on op) the hierarchy for opts o
+ * (NULL: defaults), then runs gmg_pcg_run. */
 int gmg_pcg_solve(pa_op_t* op, const double* b, double* x, double rtol, const pa_solve_opts_t* o,
                   pa_solve_info_t* info);
 
