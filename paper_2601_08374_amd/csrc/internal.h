@@ -91,12 +91,13 @@ constexpr int kLinTX = 8, kLinTY = 8;
 // Wavefronts the GPU holds at once for that kernel: 256 CUs x 4 SIMDs x 2 waves.
 constexpr int kLinWaveSlots = 2048;
 
-// z-chunk length for an n[0] x n[1] x n[2] mesh: the smallest length >= 4 with which all
-// (column tile, z-chunk) wavefronts are resident at once -- one round of waves, no tail,
-// and few tile faces across z.
+// z-chunk length for an n[0] x n[1] x n[2] mesh: the smallest length with which all
+// (column tile, z-chunk) wavefronts are resident at once -- one round of waves, no tail.
+// Small meshes get short chunks (down to one element), so that more wavefronts share the
+// work; large ones as few tile faces across z as fill the GPU once.
 inline int lin_chunk(const int n[3]) {
     const int64_t nxy = (int64_t)((n[0] + kLinTX - 1) / kLinTX) * ((n[1] + kLinTY - 1) / kLinTY);
-    int L = 4;
+    int L = 1;
     while (L < n[2] && nxy * ((n[2] + L - 1) / L) > kLinWaveSlots) ++L;
     return L;
 }
