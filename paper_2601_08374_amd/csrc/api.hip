@@ -88,7 +88,7 @@ int validate_mesh(const pa_mesh_t* m, MeshDesc* out) {
 
 // Build an operator from a validated mesh description (also used for solver levels).
 int create_op(const MeshDesc& md, int p, int q, const double* lam, const double* mu, int dtype, hipStream_t s,
-              pa_op** out, bool lin_kernel) {
+              pa_op** out, int lin_mode) {
     if (p < 1) return fail(PA_EINVAL, "p = %d must be >= 1", p);
     if (p > kMaxP) return fail(PA_EUNSUPPORTED, "p = %d > %d is not built", p, kMaxP);
     if (q < p + 1 || q > p + 3) return fail(PA_EINVAL, "q = %d must be in [p+1, p+3] = [%d, %d]", q, p + 1, p + 3);
@@ -113,7 +113,8 @@ int create_op(const MeshDesc& md, int p, int q, const double* lam, const double*
     op->Nn = Nn;
     op->N = 3 * Nn;
     op->stream = s;
-    op->sk_bytes = (size_t)skeleton_words(p, md.n, lin_kernel) * (dtype == PA_F64 ? sizeof(double) : sizeof(float));
+    op->lin = p == 1 && p1_runs_lin(md.n, lin_mode);
+    op->sk_bytes = (size_t)skeleton_words(p, md.n, lin_mode) * (dtype == PA_F64 ? sizeof(double) : sizeof(float));
     op->lam.assign(lam, lam + NE);
     op->mu.assign(mu, mu + NE);
     pa_solve_opts_default(&op->cached_opts);
@@ -227,6 +228,7 @@ int apply_op(const pa_op* op, const void* x, void* y, int flags, void* sk) {
     L.gd = op->gd;
     L.tab = &op->tab;
     L.add = add;
+    L.lin = op->lin;
     L.stream = op->stream;
     const int qo = op->q - op->p - 1;
     switch (op->p) {
@@ -253,7 +255,7 @@ int create_material_op(const MeshDesc& md, int p, int q, int kind, const double*
     // p = 1 with per-point Lame data runs in the linear-element kernel (one lane per element),
     // which reads the data point-major: word k of point alpha of element e at (2 alpha + k) NE + e
     const bool lin = p == 1 && kind == PA_MAT_QP_ISO;
-    int rc = create_op(md, p, q, one.data(), one.data(), dtype, s, &op, lin);
+    int rc = create_op(md, p, q, one.data(), one.data(), dtype, s, &op, lin ? kLinAlways : kLinNever);
     if (rc) return rc;
     op->mat = kind;
     op->md_point_major = lin;

@@ -675,9 +675,12 @@ int launch_apply_p1(const ApplyLaunch& L, int q_off, int dtype) {
     if (L.geo != PA_GEOM_AFFINE) return launch_apply_geometry<1>(L, q_off, dtype);
     if (L.mat == PA_MAT_QP_ISO) {
         if (q_off != 1) return fail(PA_EUNSUPPORTED, "general material data is built for q = p + 2 only");
+        if (!L.lin) return fail(PA_EINVAL, "per-point p = 1 data is laid out for the linear-element kernel");
         return dtype == PA_F64 ? launch_lin<3, double, true>(L) : launch_lin<3, float, true>(L);
     }
     if (L.mat != PA_MAT_ELEM_ISO) return launch_apply_material<1>(L, q_off, dtype);
+    // small meshes: the sum-factorized kernel (see p1_runs_lin)
+    if (!L.lin) return launch_apply_p<1>(L, q_off, dtype);
     if (dtype == PA_F64) {
         switch (q_off) {
             case 0: return launch_lin<2, double>(L);

@@ -204,7 +204,7 @@ extern "C" int pa_elast_setup_geometry(const pa_mesh_t* m, const double* vertice
     for (int64_t i = 0; i < 3 * NV; ++i)
         if (!std::isfinite(vertices[i])) return fail(PA_EINVAL, "vertex coordinate %lld is not finite", (long long)i);
     pa_op* op = nullptr;
-    rc = create_op(md, p, q, lambda, mu, dtype, (hipStream_t)hip_stream, &op, false);
+    rc = create_op(md, p, q, lambda, mu, dtype, (hipStream_t)hip_stream, &op, kLinNever);
     if (rc) return rc;
     op->geo = kind;
     std::vector<double> coef;

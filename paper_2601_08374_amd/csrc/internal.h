@@ -70,6 +70,7 @@ struct ApplyLaunch {
     int n_sk = 0;
     const Tables* tab;
     int add;             // accumulate into y (y pre-initialised by the caller)
+    bool lin = false;    // p = 1: the linear-element kernel (the operator's skeleton buffer is sized for it)
     hipStream_t stream;
 };
 
@@ -102,6 +103,19 @@ inline int lin_chunk(const int n[3]) {
     return L;
 }
 
+// Which kernel a p = 1 operator runs: the sum-factorized kernel (kLinNever), the linear-element
+// kernel (kLinAlways: per-point Lame data, stored point-major for it), or the linear-element
+// kernel on meshes of more than kLinSmallMesh elements (kLinBySize).  The linear-element kernel
+// walks each lane's chunk of elements in sequence, which on small meshes leaves most of the GPU
+// idle; there the sum-factorized kernel, which spreads an element over nine lanes, is faster
+// (measured crossover between 32^3 and 48^3 elements).
+enum : int { kLinNever = 0, kLinBySize = 1, kLinAlways = 2 };
+constexpr int64_t kLinSmallMesh = 32768;
+inline bool p1_runs_lin(const int n[3], int lin_mode) {
+    const int64_t NE = (int64_t)n[0] * n[1] * n[2];
+    return lin_mode == kLinAlways || (lin_mode == kLinBySize && NE > kLinSmallMesh);
+}
+
 // Words per tile and component of the linear-element skeleton buffer: the tile's
 // boundary nodes in three face arrays, each contiguous along its face (x faces
 // [2][tz+1][TY+1], y faces [2][tz+1][TX+1], z faces [2][TY+1][TX+1]).
@@ -115,10 +129,10 @@ inline int64_t lin_tiles(const int n[3], int tz) {
 }
 
 // Words of the skeleton buffer of one operator: per element, 3 components x its
-// element-boundary nodes; for the linear-element kernel (p = 1, lin_kernel),
-// 3 components x the node box of every tile.
-inline int64_t skeleton_words(int p, const int n[3], bool lin_kernel = true) {
-    if (p == 1 && lin_kernel) {
+// element-boundary nodes; for the linear-element kernel (p = 1, see p1_runs_lin),
+// 3 components x the face nodes of every tile.
+inline int64_t skeleton_words(int p, const int n[3], int lin_mode = kLinBySize) {
+    if (p == 1 && p1_runs_lin(n, lin_mode)) {
         const int tz = lin_chunk(n);
         return lin_tiles(n, tz) * 3 * lin_face_words(tz);
     }
@@ -165,6 +179,7 @@ struct pa_op {
     int mat = PA_MAT_ELEM_ISO;       // material data form
     void* md = nullptr;              // device material data of dtype (PA_MAT_QP_ISO, PA_MAT_ANISO)
     bool md_point_major = false;     // md word k of point alpha of element e at (2 alpha + k) NE + e
+    bool lin = false;                // p = 1: applies run the linear-element kernel
     std::vector<double> mdata;       // host copy of per-point Lame data [NE][q^3][2] (solver hierarchies)
     int geo = PA_GEOM_AFFINE;        // element geometry form
     void* gd = nullptr;              // device geometry data of dtype (PA_GEOM_QP_DATA, PA_GEOM_TRILINEAR)

@@ -53,11 +53,11 @@ int compute_element_data(const MeshDesc& m, const double* d_vert, const double* 
                          int dtype, void* ed, hipStream_t s);
 int launch_diagonal(const pa_op* op, void* d, int constrained);
 int validate_mesh(const pa_mesh_t* m, MeshDesc* out);
-// An operator on a validated mesh (also used for solver levels).  lin_kernel: p = 1
-// applies run the linear-element kernel (per-element Lame data on the affine box);
-// false sizes the skeleton buffer for the sum-factorized kernel instead.
+// An operator on a validated mesh (also used for solver levels).  lin_mode: which kernel
+// p = 1 applies run (kLinNever / kLinBySize / kLinAlways, see p1_runs_lin); the skeleton
+// buffer is sized for it.
 int create_op(const MeshDesc& md, int p, int q, const double* lam, const double* mu, int dtype, hipStream_t s,
-              pa_op** out, bool lin_kernel = true);
+              pa_op** out, int lin_mode = kLinBySize);
 // geometry.hip
 void element_map_coefficients(const double* const X[8], double* o);
 int finish_geometry(pa_op* op, const std::vector<double>& coef, const double* lam, const double* mu);

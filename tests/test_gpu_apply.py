@@ -77,18 +77,36 @@ def test_apply_parity_all_orders(p, q, dtype):
         assert _rel(y, ref) <= TOL[dtype], (flags, _rel(y, ref))
 
 
+def _two_step_grade(n, L, ratio=1.6):
+    """Vertex coordinates alternating between two spacings (a few distinct element sizes)."""
+    h = np.where(np.arange(n) % 2 == 0, 1.0, ratio)
+    x = np.concatenate([[0.0], np.cumsum(h)])
+    return x * (L / x[-1])
+
+
 @pytest.mark.parametrize("q", [2, 3, 4])
 @pytest.mark.parametrize("dtype", [0, 1])
-def test_apply_p1_tiles(q, dtype):
-    """Linear elements: a mesh spanning several 8x8x4-element tiles with ragged tails on every
-    axis (interior, face, edge and corner nodes shared between tiles), clamped on three faces."""
+@pytest.mark.parametrize("size", ["small", "tiles", "chunks"])
+def test_apply_p1_tiles(q, dtype, size):
+    """Linear elements, clamped on three faces, with ragged tails on every axis: a small graded
+    mesh (at most 32768 elements: the sum-factorized kernel), and two meshes above that size
+    (the linear-element kernel) spanning many 8x8-column tiles: 35 x 37 x 27 (one-element
+    z-chunks) and 130 x 130 x 9 (two-element chunks with a one-element last chunk), graded with
+    two spacings per axis (interior, face, edge and corner nodes shared between tiles)."""
     pa = _pa()
-    print(f"p=1 tiles q={q} dtype={dtype}", flush=True)
-    mesh = syn.graded_mesh((19, 11, 9), seed=4, L=(1.9, 1.1, 0.9), A=syn.random_rotation(4) @ syn.SHEAR_A,
+    print(f"p=1 tiles size={size} q={q} dtype={dtype}", flush=True)
+    A = syn.random_rotation(4) @ syn.SHEAR_A
+    if size == "small":
+        mesh = syn.graded_mesh((19, 11, 9), seed=4, L=(1.9, 1.1, 0.9), A=A, clamped_faces=0b100101)
+        rng = np.random.default_rng(41)
+        lam, mu = rng.uniform(0.2, 3.0, mesh.num_elements), rng.uniform(0.2, 3.0, mesh.num_elements)
+    else:
+        n = (35, 37, 27) if size == "tiles" else (130, 130, 9)
+        L = (1.9, 1.7, 1.2)
+        mesh = syn.BoxMesh(n=n, L=L, A=A, grade=[_two_step_grade(n[a], L[a]) for a in range(3)],
                            clamped_faces=0b100101)
-    NE = mesh.num_elements
-    rng = np.random.default_rng(41)
-    lam, mu = rng.uniform(0.2, 3.0, NE), rng.uniform(0.2, 3.0, NE)
+        assert mesh.num_elements > 32768
+        lam, mu = syn.two_material_lame(mesh.num_elements, seed=6)
     x = syn.uniform_vector(mesh.num_dofs(1), seed=5)
     op_ref = elasticity.Operator(mesh, 1, q, lam, mu)
     for flags, constrained in ((0, True), (1, False)):
@@ -100,8 +118,8 @@ def test_apply_p1_tiles(q, dtype):
 @pytest.mark.parametrize("dtype", [0, 1])
 def test_apply_p1_long_chunks(dtype):
     """Linear elements on a wide, thin mesh (400 x 400 x 5): more column tiles than the GPU holds
-    waves for, so every lane walks the whole z extent in one chunk (longer than the 4-element
-    minimum); full output against the oracle, two materials, clamped on two faces."""
+    waves for, so every lane walks the whole z extent in one chunk; full output against the
+    oracle, two materials, clamped on two faces."""
     pa = _pa()
     print(f"p=1 long chunks dtype={dtype}", flush=True)
     mesh = syn.BoxMesh(n=(400, 400, 5), L=(2.0, 2.0, 0.025), A=syn.SHEAR_A, clamped_faces=0b010001)
