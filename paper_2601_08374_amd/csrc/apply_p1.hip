@@ -1,18 +1,18 @@
 // Apply for linear elements (p = 1): register-resident, one lane per element.
 //
-// The steps are those of the fused kernel (paper Sec. 4.2, 4.4, 4.5): forward
-// X/Y/Z sum-factorization sweeps to the reference gradient, pointwise Voigt
-// stress with w*detJ*lambda, w*detJ*mu and Q = sigma J^{-T} (eq. 7), transposed
-// sweeps back to the nodes.  With two nodes per axis the whole element state
-// fits in registers, so each lane runs them for its own element with loops
-// over the quadrature points: no LDS, no barriers.  The derivative of the
-// linear Lagrange basis on [0,1] is -1 and +1 at every point, so every
-// derivative contraction is a difference.
+// The operator is that of the fused kernel (paper Sec. 4.2, 4.4, 4.5): reference
+// gradient, pointwise Voigt stress with w*detJ*lambda, w*detJ*mu and Q = sigma J^{-T}
+// (eq. 7), tested against the basis gradients.  With two nodes per axis the whole
+// element state fits in registers, so each lane runs an element by itself: no LDS
+// (except for the nodal values of the double-precision per-point kernel), no barriers.
+// With per-element Lame data every factor of the quadrature sum is a polynomial of
+// degree at most one per axis, and the sum collapses to one term per monomial
+// (lin_element_closed); per-point Lame data keeps the point loops (lin_element).
 //
 // A wavefront is a tile of kLinTX x kLinTY element columns (lane = column);
 // each lane walks a chunk of lin_chunk() elements up its column, carrying the upper face of
-// one element (x values and partial results) in registers into the next, and
-// prefetching the next element's x face and PA data while it computes.  After
+// one element (x values and partial results) in registers into the next (the per-point
+// kernels also prefetch the next element's x face and data while they compute).  After
 // each element the finished node layer is summed across lanes with shuffles
 // (x neighbour, then y neighbour); every node of the layer has one owning
 // lane, which writes y itself when all elements touching the node lie in the
@@ -29,7 +29,7 @@ struct LinTabs {
     T B0[Q], B1[Q];   // linear Lagrange basis at the Gauss-Legendre points: 1 - xi_k, xi_k
     T w[Q];           // Gauss-Legendre weights on [0,1]
     T wzy[Q * Q];     // w[qz] * w[qy]
-    T wm[3];          // moments of the rule: sum_k w[k] xi_k^m, m = 0, 1, 2
+    T cb[3];          // lin_element_closed: beta_n = 4^(n-2) W0^(3-n) W2^n, W_m = sum_k w[k] (xi_k - 1/2)^m
 };
 
 // 12 words of per-element data with 16-byte loads (the rows are 48 or 96 bytes).
@@ -69,30 +69,23 @@ __device__ __forceinline__ size_t lin_slot(int t, int c, int lz, int ly, int lx,
     return base + ofs_z + ((size_t)(lz != 0) * (kLinTY + 1) + ly) * (kLinTX + 1) + lx;
 }
 
-// One (qy, qz) column of quadrature points: forward X to the reference gradient
-// g[c][m], pointwise stress (weights w[qx] * lzy, mzy) and its two Voigt moments along the
-// column, from which lin_project forms the backward X channels of Q = sigma J^{-T}: S0
-// (G_x channel, summed over qx) and r1, r2 (B_x channels).
+// One (qy, qz) column of quadrature points with per-point Lame parameters lq[qx], mq[qx]:
+// forward X to the reference gradient, pointwise stress (weights w[qx] * lzy * lq[qx],
+// w[qx] * mzy * mq[qx]; lzy, mzy carry w[qz] w[qy] det J) and its two Voigt moments along the
+// column, M0 = sum w sigma and M1 = sum w xi sigma, from which lin_project forms the
+// backward X channels of Q = sigma J^{-T}.
 // Inputs per component c and x-column ix: a = B_y B_z x, b = G_y B_z x, e = B_y G_z x.
-// QPM: per-point Lame parameters lq[qx], mq[qx] of the column scale lzy, mzy (which then
-// carry w det J only).
 //
 // With the linear basis in x, B_x(xi) = (1 - xi, xi) and G_x = (-1, 1), so along the
 // column the reference gradient is linear in xi: g = (a1 - a0, b0 + xi (b1 - b0),
 // e0 + xi (e1 - e0)), and so is the physical gradient, du = D0 + xi D1 (both J^{-T}
-// products formed once per column).  On the way
-// back, J^{-1} is constant over the element, so the x sums of Q = sigma J^{-T} are
-// J^{-1} applied to the x sums of sigma, the moments M0 = sum w sigma and
-// M1 = sum w xi sigma (6 Voigt entries each), and
+// products formed once per column).  On the way back, J^{-1} is constant over the element,
+// so the x sums of Q = sigma J^{-T} are J^{-1} applied to the x sums of sigma:
 // S0 = sum Q_0 = M0 J^{-1}_0, r_m = (sum (1 - xi) Q_m, sum xi Q_m) = ((M0 - M1) J^{-1}_m, M1 J^{-1}_m).
-// With the Lame weights constant along the column the stress is linear in xi as well,
-// sigma = s0 + xi s1 (s0, s1 the stresses of D0 and D1), so the point sums reduce to the
-// rule's moments W_m = sum w xi^m: M0 = W0 s0 + W1 s1, M1 = W1 s0 + W2 s1 (the same sums,
-// regrouped).  Per-point Lame data (QPM) sums the stress point by point.
-template <int Q, typename T, bool QPM = false>
+template <int Q, typename T>
 __device__ __forceinline__ void lin_moments(const T (&a)[3][2], const T (&b)[3][2], const T (&e)[3][2],
                                             const T (&Ji)[9], const T lzy, const T mzy, const LinTabs<T, Q>& tb,
-                                            T (&M0)[6], T (&M1)[6], const T* lq = nullptr, const T* mq = nullptr) {
+                                            T (&M0)[6], T (&M1)[6], const T (&lq)[Q], const T (&mq)[Q]) {
     T D0[3][3], D1[3][3];   // du[c][i] = d u_c / d x_i = D0[c][i] + xi D1[c][i]
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -104,50 +97,30 @@ __device__ __forceinline__ void lin_moments(const T (&a)[3][2], const T (&b)[3][
         }
     }
     // Voigt moments: entries (xx, yy, zz, yz, xz, xy)
-    if constexpr (!QPM) {
-        auto voigt = [&](const T (&G)[3][3], T (&sv)[6]) {
-            const T ld = lzy * (G[0][0] + G[1][1] + G[2][2]), m2 = mzy + mzy;
-            sv[0] = ld + m2 * G[0][0];
-            sv[1] = ld + m2 * G[1][1];
-            sv[2] = ld + m2 * G[2][2];
-            sv[3] = mzy * (G[1][2] + G[2][1]);
-            sv[4] = mzy * (G[0][2] + G[2][0]);
-            sv[5] = mzy * (G[0][1] + G[1][0]);
-        };
-        T s0[6], s1[6];
-        voigt(D0, s0);
-        voigt(D1, s1);
+#pragma unroll
+    for (int v = 0; v < 6; ++v) M0[v] = M1[v] = T(0);
+#pragma unroll
+    for (int qx = 0; qx < Q; ++qx) {
+        const T xi = tb.B1[qx];
+        const T lam = lzy * tb.w[qx] * lq[qx], mu = mzy * tb.w[qx] * mq[qx];
+        T du[3][3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) du[c][i] = fma(xi, D1[c][i], D0[c][i]);
+        const T div = du[0][0] + du[1][1] + du[2][2];
+        const T ld = lam * div, m2 = mu + mu;
+        T sv[6];
+        sv[0] = ld + m2 * du[0][0];
+        sv[1] = ld + m2 * du[1][1];
+        sv[2] = ld + m2 * du[2][2];
+        sv[3] = mu * (du[1][2] + du[2][1]);
+        sv[4] = mu * (du[0][2] + du[2][0]);
+        sv[5] = mu * (du[0][1] + du[1][0]);
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
-            M0[v] = fma(tb.wm[1], s1[v], tb.wm[0] * s0[v]);
-            M1[v] = fma(tb.wm[2], s1[v], tb.wm[1] * s0[v]);
-        }
-    } else {
-#pragma unroll
-        for (int v = 0; v < 6; ++v) M0[v] = M1[v] = T(0);
-#pragma unroll
-        for (int qx = 0; qx < Q; ++qx) {
-            const T xi = tb.B1[qx];
-            const T lam = lzy * tb.w[qx] * lq[qx], mu = mzy * tb.w[qx] * mq[qx];
-            T du[3][3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int i = 0; i < 3; ++i) du[c][i] = fma(xi, D1[c][i], D0[c][i]);
-            const T div = du[0][0] + du[1][1] + du[2][2];
-            const T ld = lam * div, m2 = mu + mu;
-            T sv[6];
-            sv[0] = ld + m2 * du[0][0];
-            sv[1] = ld + m2 * du[1][1];
-            sv[2] = ld + m2 * du[2][2];
-            sv[3] = mu * (du[1][2] + du[2][1]);
-            sv[4] = mu * (du[0][2] + du[2][0]);
-            sv[5] = mu * (du[0][1] + du[1][0]);
-#pragma unroll
-            for (int v = 0; v < 6; ++v) {
-                M0[v] += sv[v];
-                M1[v] = fma(xi, sv[v], M1[v]);
-            }
+            M0[v] += sv[v];
+            M1[v] = fma(xi, sv[v], M1[v]);
         }
     }
 }
@@ -181,15 +154,13 @@ __device__ __forceinline__ void lin_project(const T (&M0)[6], const T (&M1)[6], 
 
 // Per-point material (QPM): mdp points at the element's (lambda, mu) of point 0; point
 // alpha, word k is mdp[(2 alpha + k) * ns] (point-major layout, elements contiguous).
-template <int Q, typename T, bool QPM>
+template <int Q, typename T>
 __device__ __forceinline__ void lin_point_lame(const T* mdp, size_t ns, int qz, int qy, T (&lq)[Q], T (&mq)[Q]) {
-    if constexpr (QPM) {
 #pragma unroll
-        for (int qx = 0; qx < Q; ++qx) {
-            const size_t al = qx + Q * (qy + Q * qz);
-            lq[qx] = mdp[(2 * al) * ns];
-            mq[qx] = mdp[(2 * al + 1) * ns];
-        }
+    for (int qx = 0; qx < Q; ++qx) {
+        const size_t al = qx + Q * (qy + Q * qz);
+        lq[qx] = mdp[(2 * al) * ns];
+        mq[qx] = mdp[(2 * al + 1) * ns];
     }
 }
 
@@ -236,19 +207,16 @@ struct LinNodesReg {
     static constexpr int kStride = 1;
 };
 
-// Element contribution y_e = K_e x_e of one element, added to ya (lower face iz = 0) and
-// yb (upper face iz = 1); word k of a face is (c, iy, ix) = (k >> 2, (k >> 1) & 1, k & 1).
-// nd holds the element's nodal values in difference form (word w at nd[w * Src::kStride]).
-// Per (qz, qy) column: the forward Y/Z interpolation (four FMAs per x-column), the
-// column's Voigt moments (lin_moments).  With per-element Lame weights the backward X
-// channels are linear in the moments, so a z layer sums the moments of its columns and
-// eta times them, and projects the sums once (the layer sums of S0, eta S0, r1, r2 and
-// eta r2), then runs the backward Y sweep (B_y = (1 - eta, eta), G_y = (-1, 1)) and the
-// backward Z sweep into the faces.  Per-point material (QPM) projects every column and
-// sweeps it back by itself.
-template <int Q, typename T, bool QPM, typename Src>
+// Element contribution y_e = K_e x_e of one element with per-point Lame data, added to ya
+// (lower face iz = 0) and yb (upper face iz = 1); word k of a face is (c, iy, ix) =
+// (k >> 2, (k >> 1) & 1, k & 1).  nd holds the element's nodal values in difference form
+// (word w at nd[w * Src::kStride]).  Per (qz, qy) column: the forward Y/Z interpolation
+// (four FMAs per x-column), the column's Voigt moments (lin_moments), their projection
+// (lin_project), the backward Y sweep (B_y = (1 - eta, eta), G_y = (-1, 1)) and the
+// backward Z sweep into the faces.
+template <int Q, typename T, typename Src>
 __device__ __forceinline__ void lin_element(const T* nd, const T (&d)[12], const LinTabs<T, Q>& tb,
-                                            T (&ya)[12], T (&yb)[12], const T* mdp = nullptr, size_t ns = 0) {
+                                            T (&ya)[12], T (&yb)[12], const T* mdp, size_t ns) {
     constexpr int stride = Src::kStride;
     T Ji[9];
 #pragma unroll
@@ -257,14 +225,10 @@ __device__ __forceinline__ void lin_element(const T* nd, const T (&d)[12], const
 #pragma unroll 1
     for (int qz = 0; qz < Q; ++qz) {
         const T bz0 = tb.B0[qz], bz1 = tb.B1[qz];
-        // sums over the layer's columns of the Voigt moments and eta times them
-        T hM0[6], hM1[6], hE0[6], hE1[6];
-#pragma unroll
-        for (int v = 0; v < 6; ++v) hM0[v] = hM1[v] = hE0[v] = hE1[v] = T(0);
 #pragma unroll 1
         for (int qy = 0; qy < Q; ++qy) {
             if constexpr (Src::kLds) lds_reload_point();
-            const T by1 = tb.B1[qy];
+            const T by0 = tb.B0[qy], by1 = tb.B1[qy];
             const T wzy = tb.wzy[qz * Q + qy];
             // a = B_y B_z x, b = G_y B_z x, e = B_y G_z x at (eta, zeta) = (by1, bz1)
             T a[3][2], b[3][2], e[3][2];
@@ -280,62 +244,177 @@ __device__ __forceinline__ void lin_element(const T* nd, const T (&d)[12], const
                     e[c][ix] = fma(by1, nyz, nz);
                 }
             T M0[6], M1[6], lq[Q], mq[Q];
-            lin_point_lame<Q, T, QPM>(mdp, ns, qz, qy, lq, mq);
-            lin_moments<Q, T, QPM>(a, b, e, Ji, lw * wzy, mw * wzy, tb, M0, M1, lq, mq);
-            if constexpr (QPM) {
-                // t0 = B_y S0 (sign of G_x by ix) + G_y r1 takes B_z, t2 = B_y r2 takes G_z = (-1, +1)
-                T S0[3], r1[3][2], r2[3][2];
-                lin_project(M0, M1, Ji, S0, r1, r2);
-                const T by0 = tb.B0[qy];
+            lin_point_lame<Q, T>(mdp, ns, qz, qy, lq, mq);
+            lin_moments<Q, T>(a, b, e, Ji, lw * wzy, mw * wzy, tb, M0, M1, lq, mq);
+            // t0 = B_y S0 (sign of G_x by ix) + G_y r1 takes B_z, t2 = B_y r2 takes G_z = (-1, +1)
+            T S0[3], r1[3][2], r2[3][2];
+            lin_project(M0, M1, Ji, S0, r1, r2);
 #pragma unroll
-                for (int c = 0; c < 3; ++c)
+            for (int c = 0; c < 3; ++c)
 #pragma unroll
-                    for (int iy = 0; iy < 2; ++iy) {
-                        const T by = iy ? by1 : by0;
-#pragma unroll
-                        for (int ix = 0; ix < 2; ++ix) {
-                            const int k = c * 4 + iy * 2 + ix;
-                            const T t0 = (ix ? by : -by) * S0[c] + (iy ? r1[c][ix] : -r1[c][ix]);
-                            const T t2 = by * r2[c][ix];
-                            ya[k] += bz0 * t0 - t2;
-                            yb[k] += bz1 * t0 + t2;
-                        }
-                    }
-            } else {
-#pragma unroll
-                for (int v = 0; v < 6; ++v) {
-                    hM0[v] += M0[v];
-                    hM1[v] += M1[v];
-                    hE0[v] = fma(by1, M0[v], hE0[v]);
-                    hE1[v] = fma(by1, M1[v], hE1[v]);
-                }
-            }
-        }
-        if constexpr (!QPM) {
-            T hS[3], hr1[3][2], hr2[3][2], hSe[3], hr1e[3][2], hr2e[3][2];
-            lin_project(hM0, hM1, Ji, hS, hr1, hr2);
-            lin_project(hE0, hE1, Ji, hSe, hr1e, hr2e);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const T sy0 = hS[c] - hSe[c];
-#pragma unroll
-                for (int iy = 0; iy < 2; ++iy)
+                for (int iy = 0; iy < 2; ++iy) {
+                    const T by = iy ? by1 : by0;
 #pragma unroll
                     for (int ix = 0; ix < 2; ++ix) {
                         const int k = c * 4 + iy * 2 + ix;
-                        const T sy = iy ? hSe[c] : sy0;
-                        const T t0 = (ix ? sy : -sy) + (iy ? hr1[c][ix] : -hr1[c][ix]);
-                        const T t2 = iy ? hr2e[c][ix] : hr2[c][ix] - hr2e[c][ix];
+                        const T t0 = (ix ? by : -by) * S0[c] + (iy ? r1[c][ix] : -r1[c][ix]);
+                        const T t2 = by * r2[c][ix];
                         ya[k] += bz0 * t0 - t2;
                         yb[k] += bz1 * t0 + t2;
                     }
-            }
+                }
         }
     }
 }
 
+// One monomial t (bit k = power of s_k, t != 7) of lin_element_closed: the physical gradient
+// coefficient Dt = sum_{k: t_k = 0} H_{t + e_k} (x) J^{-1}_k (row k of J^{-1}), its stress with
+// the weights lt, mt, and P[k][c] = (sigma J^{-T})[c][k] for the k with t_k = 0.
+template <int t, typename T>
+__device__ __forceinline__ void lin_monomial(const T (&h)[8][3], const T (&Ji)[9], const T lt, const T mt,
+                                             T (&P)[3][3]) {
+    T D[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            T acc = T(0);
+            bool first = true;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                if ((t >> k) & 1) continue;
+                const T hv = h[t | (1 << k)][c];
+                acc = first ? hv * Ji[k * 3 + j] : fma(hv, Ji[k * 3 + j], acc);
+                first = false;
+            }
+            D[c][j] = acc;
+        }
+    const T ld = lt * (D[0][0] + D[1][1] + D[2][2]), m2 = mt + mt;
+    T S[3][3];
+    S[0][0] = fma(m2, D[0][0], ld);
+    S[1][1] = fma(m2, D[1][1], ld);
+    S[2][2] = fma(m2, D[2][2], ld);
+    S[1][2] = S[2][1] = mt * (D[1][2] + D[2][1]);
+    S[0][2] = S[2][0] = mt * (D[0][2] + D[2][0]);
+    S[0][1] = S[1][0] = mt * (D[0][1] + D[1][0]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if ((t >> k) & 1) continue;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) P[k][c] = fma(S[c][2], Ji[k * 3 + 2], fma(S[c][1], Ji[k * 3 + 1], S[c][0] * Ji[k * 3]));
+    }
+}
+
+// Element contribution of one element with per-element Lame weights (d[9] = det J lambda,
+// d[10] = det J mu), added to ya (lower face) and stored to yb (upper face); fa, fb are the element's
+// lower and upper x faces (word k = (c, iy, ix) as above).
+//
+// In centred coordinates s = xi - 1/2 the basis is prod_k (1/2 + sgn(i_k) s_k), sgn(0) = -1,
+// sgn(1) = +1, so the nodal interpolant is u = sum_a 2^(|a|-3) H_a s^a over a in {0,1}^3,
+// where H_a = sum_i x_i prod_k sgn(i_k)^(a_k) is the 8-point Walsh-Hadamard transform of the
+// nodal values.  J^{-1} and the Lame weights are constant over the element, so the physical
+// gradient, the stress and Q = sigma J^{-T} are sums over the monomials t != (1,1,1), and
+// the test gradients d phi_i / d xi_k are sums over the monomials with t_k = 0.  The
+// quadrature sum of a product of two monomials is a product of the rule's centred 1D
+// moments W_m = sum w s^m; the Gauss rule is symmetric, so its odd moments vanish and only
+// equal monomials pair up, with weight W0^(3-|t|) W2^|t|.  With the powers of 2 folded in
+// (beta_n = 4^(n-2) W0^(3-n) W2^n, LinTabs::cb), the element vector is
+//   y_i = sum_a prod_k sgn(i_k)^(a_k) Y_a,   Y_a = sum_{k: a_k = 1} P_{a - e_k}[k],
+//   P_t = beta_|t| sigma(Dt) J^{-T},          Dt = sum_{k: t_k = 0} H_{t + e_k} (x) J^{-1}_k:
+// the same quadrature sums as the point loops, regrouped, in about a quarter of their
+// operations.
 template <typename T>
-constexpr bool kLinXInLds = sizeof(T) == 8;
+__device__ __forceinline__ void lin_element_closed(const T (&fa)[12], const T (&fb)[12], const T (&d)[12],
+                                                   const T (&cb)[3], T (&ya)[12], T (&yb)[12]) {
+    // h[a][c], a = ax + 2 ay + 4 az; node i = ix + 2 iy + 4 iz
+    T h[8][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = (i & 4) ? fb[c * 4 + (i & 3)] : fa[c * 4 + (i & 3)];
+#pragma unroll
+        for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (!(j & bit)) {
+                    const T lo = v[j], hi = v[j | bit];
+                    v[j] = hi + lo;
+                    v[j | bit] = hi - lo;
+                }
+#pragma unroll
+        for (int a = 0; a < 8; ++a) h[a][c] = v[a];
+    }
+    T Ji[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Ji[k] = d[k];
+    const T l0 = cb[0] * d[9], m0 = cb[0] * d[10];
+    const T l1 = cb[1] * d[9], m1 = cb[1] * d[10];
+    const T l2 = cb[2] * d[9], m2 = cb[2] * d[10];
+    // Y[a][c]; the monomials in an order that lets each H_a die early
+    T Y[8][3], P[3][3];
+    lin_monomial<0>(h, Ji, l0, m0, P);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Y[1][c] = P[0][c];
+        Y[2][c] = P[1][c];
+        Y[4][c] = P[2][c];
+    }
+    lin_monomial<1>(h, Ji, l1, m1, P);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Y[3][c] = P[1][c];
+        Y[5][c] = P[2][c];
+    }
+    lin_monomial<2>(h, Ji, l1, m1, P);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Y[3][c] += P[0][c];
+        Y[6][c] = P[2][c];
+    }
+    lin_monomial<4>(h, Ji, l1, m1, P);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Y[5][c] += P[0][c];
+        Y[6][c] += P[1][c];
+    }
+    lin_monomial<3>(h, Ji, l2, m2, P);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Y[7][c] = P[2][c];
+    lin_monomial<5>(h, Ji, l2, m2, P);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Y[7][c] += P[1][c];
+    lin_monomial<6>(h, Ji, l2, m2, P);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Y[7][c] += P[0][c];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T v[8];
+        v[0] = T(0);
+#pragma unroll
+        for (int a = 1; a < 8; ++a) v[a] = Y[a][c];
+        // y_i = sum_a prod_k sgn(i_k)^(a_k) v_a, one axis at a time
+#pragma unroll
+        for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (!(j & bit)) {
+                    const T lo = v[j], hi = v[j | bit];
+                    v[j] = lo - hi;
+                    v[j | bit] = lo + hi;
+                }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (i & 4) yb[c * 4 + (i & 3)] = v[i];
+            else ya[c * 4 + (i & 3)] += v[i];
+        }
+    }
+}
+
+// the double-precision per-point kernel keeps the element's nodal values in LDS (its point
+// loops need more than 256 VGPRs with them in registers)
+template <typename T, bool QPM>
+constexpr bool kLinXInLds = QPM && sizeof(T) == 8;
 
 template <int Q, typename T, bool QPM = false>
 __global__ void __launch_bounds__(256)
@@ -433,7 +512,7 @@ pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ 
     };
 #pragma unroll
     for (int k = 0; k < 12; ++k) ya[k] = T(0);
-    if constexpr (kLinXInLds<T>) {
+    if constexpr (kLinXInLds<T, QPM>) {
         // the element's nodal values in difference form and the lower x face of the next
         // element in the lane's LDS column; the next element's data is loaded after the
         // current element (two waves per SIMD hide the latency)
@@ -462,7 +541,7 @@ pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ 
                 d[k] = dn[k];
                 yb[k] = T(0);
             }
-            lin_element<Q, T, QPM, LinNodesLds>(col, d, tb, ya, yb, mat_ptr(ez), (size_t)g.NE);
+            lin_element<Q, T, LinNodesLds>(col, d, tb, ya, yb, mat_ptr(ez), (size_t)g.NE);
             if (ez + 1 < ez1) {
                 load_face(ez + 2, xn);
                 load_data(ez + 1, dn);
@@ -473,7 +552,7 @@ pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ 
 #pragma unroll
             for (int k = 0; k < 12; ++k) ya[k] = yb[k];
         }
-    } else {
+    } else if constexpr (QPM) {
         // everything in registers; the next element's data is prefetched
         T xa[12];
         load_face(ez0, xa);
@@ -494,7 +573,28 @@ pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ 
             }
             T nd[kLinNodeWords];
             lin_node_form(xa, xb, [&](int w, T v) { nd[w] = v; });
-            lin_element<Q, T, QPM, LinNodesReg>(nd, d, tb, ya, yb, mat_ptr(ez), (size_t)g.NE);
+            lin_element<Q, T, LinNodesReg>(nd, d, tb, ya, yb, mat_ptr(ez), (size_t)g.NE);
+            T v[3][2][2];
+            to_face(ya, v);
+            emit_layer(v, ez);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                xa[k] = xb[k];
+                ya[k] = yb[k];
+            }
+        }
+    } else {
+        // per-element data, closed form: the element's upper face and data are loaded at the
+        // top of each step (prefetching them one element ahead took more registers than
+        // the two waves per SIMD this loop runs at, and measured slower)
+        T xa[12];
+        load_face(ez0, xa);
+#pragma unroll 1
+        for (int ez = ez0; ez < ez1; ++ez) {
+            T xb[12], d[12], yb[12];
+            load_face(ez + 1, xb);
+            load_data(ez, d);
+            lin_element_closed(xa, xb, d, tb.cb, ya, yb);
             T v[3][2][2];
             to_face(ya, v);
             emit_layer(v, ez);
@@ -643,11 +743,16 @@ int launch_lin(const ApplyLaunch& L) {
         tb.B1[k] = (T)L.tab->B[1 * Q + k];
         tb.w[k] = (T)L.tab->w[k];
     }
-    for (int m = 0; m < 3; ++m) {
-        double acc = 0.0;
-        for (int k = 0; k < Q; ++k) acc += L.tab->w[k] * (m == 0 ? 1.0 : m == 1 ? L.tab->B[Q + k] : L.tab->B[Q + k] * L.tab->B[Q + k]);
-        tb.wm[m] = (T)acc;
+    // centred moments of the rule (the odd ones vanish: the rule is symmetric about 1/2)
+    double W0 = 0.0, W2 = 0.0;
+    for (int k = 0; k < Q; ++k) {
+        const double s = L.tab->B[Q + k] - 0.5;
+        W0 += L.tab->w[k];
+        W2 += L.tab->w[k] * s * s;
     }
+    tb.cb[0] = (T)(W0 * W0 * W0 / 16.0);
+    tb.cb[1] = (T)(W0 * W0 * W2 / 4.0);
+    tb.cb[2] = (T)(W0 * W2 * W2);
     for (int qz = 0; qz < Q; ++qz)
         for (int qy = 0; qy < Q; ++qy) tb.wzy[qz * Q + qy] = (T)(L.tab->w[qz] * L.tab->w[qy]);
     const int n[3] = {g.nx, g.ny, g.nz};
