@@ -114,7 +114,7 @@ int create_op(const MeshDesc& md, int p, int q, const double* lam, const double*
     op->N = 3 * Nn;
     op->stream = s;
     op->lin = p == 1 && p1_runs_lin(md.n, lin_mode);
-    op->sk_bytes = (size_t)skeleton_words(p, md.n, lin_mode) * (dtype == PA_F64 ? sizeof(double) : sizeof(float));
+    op->sk_bytes = (size_t)skeleton_words(p, md.n, lin_mode, dtype) * (dtype == PA_F64 ? sizeof(double) : sizeof(float));
     op->lam.assign(lam, lam + NE);
     op->mu.assign(mu, mu + NE);
     pa_solve_opts_default(&op->cached_opts);

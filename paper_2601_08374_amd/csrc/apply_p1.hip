@@ -60,13 +60,15 @@ __device__ __forceinline__ void load_ed12(const float* p, float (&d)[12]) {
 // y-face array [side][lz][lx], the remaining ones (lz = 0 or tz) in the z-face array
 // [side][ly][lx].  Lanes that handle consecutive nodes along a face then touch consecutive
 // words, in the fused kernel and in the skeleton gather.
+__device__ __forceinline__ unsigned lin_face_slot(int lz, int ly, int lx, int tz) {
+    if (lx == 0 || lx == kLinTX) return ((unsigned)(lx == kLinTX) * (tz + 1) + lz) * (kLinTY + 1) + ly;
+    const unsigned ofs_y = 2 * (unsigned)(tz + 1) * (kLinTY + 1);
+    if (ly == 0 || ly == kLinTY) return ofs_y + ((unsigned)(ly == kLinTY) * (tz + 1) + lz) * (kLinTX + 1) + lx;
+    const unsigned ofs_z = ofs_y + 2 * (unsigned)(tz + 1) * (kLinTX + 1);
+    return ofs_z + ((unsigned)(lz != 0) * (kLinTY + 1) + ly) * (kLinTX + 1) + lx;
+}
 __device__ __forceinline__ size_t lin_slot(int t, int c, int lz, int ly, int lx, int tz) {
-    const size_t base = ((size_t)t * 3 + c) * lin_face_words(tz);
-    if (lx == 0 || lx == kLinTX) return base + ((size_t)(lx == kLinTX) * (tz + 1) + lz) * (kLinTY + 1) + ly;
-    const size_t ofs_y = 2 * (size_t)(tz + 1) * (kLinTY + 1);
-    if (ly == 0 || ly == kLinTY) return base + ofs_y + ((size_t)(ly == kLinTY) * (tz + 1) + lz) * (kLinTX + 1) + lx;
-    const size_t ofs_z = ofs_y + 2 * (size_t)(tz + 1) * (kLinTX + 1);
-    return base + ofs_z + ((size_t)(lz != 0) * (kLinTY + 1) + ly) * (kLinTX + 1) + lx;
+    return ((size_t)t * 3 + c) * lin_face_words(tz) + lin_face_slot(lz, ly, lx, tz);
 }
 
 // One (qy, qz) column of quadrature points with per-point Lame parameters lq[qx], mq[qx]:
@@ -423,7 +425,8 @@ pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ 
     constexpr int TX = kLinTX, TY = kLinTY;
     static_assert(TX * TY == 64 && kLinLds == 256, "one tile per wavefront, four per workgroup");
     const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + TZ - 1) / TZ;
-    const int tile = xcd_block(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6);
+    // one tile per wavefront: the tile and everything derived from it are wave-uniform
+    const int tile = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6));
     if (tile >= ntx * nty * ntz) return;   // the whole wavefront leaves together
     const int lane = threadIdx.x & 63;
     const int lx = lane % TX, ly = lane / TX;
@@ -435,6 +438,14 @@ pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ 
     const bool valid = ex < g.nx && ey < g.ny;
     const bool lastx = ex == tx1 - 1, lasty = ey == ty1 - 1;
     const size_t NN = (size_t)g.Nn;
+    // per-component vectors (wave-uniform bases) indexed by 32-bit node numbers (3 Nn < 2^31),
+    // and the tile's face arrays: the lanes' addresses are formed where they are used
+    const T* const xc[3] = {x, x + NN, x + 2 * NN};
+    T* const yc[3] = {y, y + NN, y + 2 * NN};
+    const size_t fw = (size_t)lin_face_words(TZ);
+    T* const skc[3] = {sk + (size_t)tile * 3 * fw, sk + ((size_t)tile * 3 + 1) * fw, sk + ((size_t)tile * 3 + 2) * fw};
+    const unsigned lane_node = (unsigned)ex + (unsigned)g.Nx * (unsigned)ey;   // node (ex, ey, 0)
+    const unsigned layer = (unsigned)g.Nx * (unsigned)g.Ny;
 
     // clamped corner nodes of the column's faces are read as 0 (constrained operator)
     auto load_face = [&](int gz, T (&f)[12]) {
@@ -442,15 +453,16 @@ pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ 
         for (int iy = 0; iy < 2; ++iy)
 #pragma unroll
             for (int ix = 0; ix < 2; ++ix) {
-                const int node = (ex + ix) + g.Nx * ((ey + iy) + g.Ny * gz);
+                const unsigned node = lane_node + layer * (unsigned)gz + (unsigned)ix + (unsigned)g.Nx * (unsigned)iy;
                 const bool use = valid && !(g.clamp && clamped_node(g.clamp, ex + ix, ey + iy, gz, g));
 #pragma unroll
-                for (int c = 0; c < 3; ++c) f[c * 4 + iy * 2 + ix] = use ? x[c * NN + node] : T(0);
+                for (int c = 0; c < 3; ++c) f[c * 4 + iy * 2 + ix] = use ? xc[c][node] : T(0);
             }
     };
     auto load_data = [&](int ez, T (&d)[12]) {
         if (valid) {
-            load_ed12(ed + (size_t)(ex + g.nx * (ey + g.ny * ez)) * kEdStride, d);
+            const unsigned e = (unsigned)ex + (unsigned)g.nx * ((unsigned)ey + (unsigned)g.ny * (unsigned)ez);
+            load_ed12(ed + (size_t)e * kEdStride, d);
         } else {
 #pragma unroll
             for (int k = 0; k < 12; ++k) d[k] = T(0);
@@ -484,17 +496,18 @@ pa_apply_lin_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ 
                 const bool cx = (gx > tx0 || gx == 0) && (gx < tx1 || gx == g.nx);
                 const bool cy = (gy > ty0 || gy == 0) && (gy < ty1 || gy == g.ny);
                 if (cx && cy && cz) {
-                    const int node = gx + g.Nx * (gy + g.Ny * gz);
+                    const unsigned node = lane_node + layer * (unsigned)gz + (unsigned)ix + (unsigned)g.Nx * (unsigned)iy;
                     const bool cl = g.clamp && clamped_node(g.clamp, gx, gy, gz, g);
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        const T val = cl ? x[c * NN + node] : v[c][iy][ix];
-                        T* yp = y + c * NN + node;
+                        const T val = cl ? xc[c][node] : v[c][iy][ix];
+                        T* yp = yc[c] + node;
                         *yp = add ? *yp + val : val;
                     }
                 } else {
+                    const unsigned slot = lin_face_slot(gz - ez0, gy - ty0, gx - tx0, TZ);
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) sk[lin_slot(tile, c, gz - ez0, gy - ty0, gx - tx0, TZ)] = v[c][iy][ix];
+                    for (int c = 0; c < 3; ++c) skc[c][slot] = v[c][iy][ix];
                 }
             }
     };
@@ -756,7 +769,7 @@ int launch_lin(const ApplyLaunch& L) {
     for (int qz = 0; qz < Q; ++qz)
         for (int qy = 0; qy < Q; ++qy) tb.wzy[qz * Q + qy] = (T)(L.tab->w[qz] * L.tab->w[qy]);
     const int n[3] = {g.nx, g.ny, g.nz};
-    const int tz = lin_chunk(n);
+    const int tz = lin_chunk(n, lin_wave_slots(sizeof(T) == 8 ? PA_F64 : PA_F32, QPM));
     const int64_t nt = lin_tiles(n, tz);
     const int nb = (int)((nt + 3) / 4);
     hipLaunchKernelGGL((pa_apply_lin_kernel<Q, T, QPM>), dim3(nb), dim3(256), 0, L.stream, (const T*)L.x, (T*)L.y,

@@ -768,7 +768,7 @@ int run_blocking(pa_gmg* G, const double* b, double* x, double rtol, pa_solve_in
 int64_t bytes_required(const MeshDesc& md, int p, int dtype, int with_solver) {
     const size_t w = wsize(dtype);
     const int64_t NE = (int64_t)md.n[0] * md.n[1] * md.n[2];
-    int64_t bytes = NE * kEdStride * (int64_t)w + skeleton_words(p, md.n) * (int64_t)w + 4096;
+    int64_t bytes = NE * kEdStride * (int64_t)w + skeleton_words(p, md.n, kLinBySize, dtype) * (int64_t)w + 4096;
     if (!with_solver) return bytes;
     pa_solve_opts_t o;
     pa_solve_opts_default(&o);
@@ -780,14 +780,14 @@ int64_t bytes_required(const MeshDesc& md, int p, int dtype, int with_solver) {
         const MeshDesc& m = plan[l].mesh;
         const int64_t n = dofs_of(m, plan[l].p);
         const int64_t ne = (int64_t)m.n[0] * m.n[1] * m.n[2];
-        bytes += (ne * kEdStride + skeleton_words(plan[l].p, m.n)) * (int64_t)vw +
+        bytes += (ne * kEdStride + skeleton_words(plan[l].p, m.n, kLinBySize, vt)) * (int64_t)vw +
                  (l + 1 < plan.size() ? 6 : 2) * n * (int64_t)vw + 65536;
     }
     const int64_t nc = dofs_of(plan.back().mesh, plan.back().p);
     bytes += nc * nc * (int64_t)(sizeof(double) + vw) + coarse_invert_words((int)nc) * (int64_t)sizeof(double);
     const int64_t n0 = dofs_of(md, p);
     bytes += 4 * n0 * (int64_t)vw;
-    if (vt == PA_F32) bytes += n0 * 4 + 2 * n0 * 8 + (NE * kEdStride + skeleton_words(p, md.n)) * 8;
+    if (vt == PA_F32) bytes += n0 * 4 + 2 * n0 * 8 + (NE * kEdStride + skeleton_words(p, md.n, kLinBySize, PA_F64)) * 8;
     return bytes;
 }
 

@@ -89,17 +89,18 @@ int launch_apply_p8(const ApplyLaunch&, int q_off, int dtype);
 // elements up its column; only nodes on the faces of such tiles go through the
 // skeleton buffer.
 constexpr int kLinTX = 8, kLinTY = 8;
-// Wavefronts the GPU holds at once for that kernel: 256 CUs x 4 SIMDs x 2 waves.
-constexpr int kLinWaveSlots = 2048;
+// Wavefronts the GPU holds at once for that kernel: 256 CUs x 4 SIMDs x the waves per SIMD
+// its registers allow -- four for per-element data in single precision, two otherwise.
+inline int lin_wave_slots(int dtype, bool point_data) { return dtype == PA_F32 && !point_data ? 4096 : 2048; }
 
 // z-chunk length for an n[0] x n[1] x n[2] mesh: the smallest length with which all
 // (column tile, z-chunk) wavefronts are resident at once -- one round of waves, no tail.
 // Small meshes get short chunks (down to one element), so that more wavefronts share the
 // work; large ones as few tile faces across z as fill the GPU once.
-inline int lin_chunk(const int n[3]) {
+inline int lin_chunk(const int n[3], int slots) {
     const int64_t nxy = (int64_t)((n[0] + kLinTX - 1) / kLinTX) * ((n[1] + kLinTY - 1) / kLinTY);
     int L = 1;
-    while (L < n[2] && nxy * ((n[2] + L - 1) / L) > kLinWaveSlots) ++L;
+    while (L < n[2] && nxy * ((n[2] + L - 1) / L) > slots) ++L;
     return L;
 }
 
@@ -131,9 +132,9 @@ inline int64_t lin_tiles(const int n[3], int tz) {
 // Words of the skeleton buffer of one operator: per element, 3 components x its
 // element-boundary nodes; for the linear-element kernel (p = 1, see p1_runs_lin),
 // 3 components x the face nodes of every tile.
-inline int64_t skeleton_words(int p, const int n[3], int lin_mode = kLinBySize) {
+inline int64_t skeleton_words(int p, const int n[3], int lin_mode, int dtype) {
     if (p == 1 && p1_runs_lin(n, lin_mode)) {
-        const int tz = lin_chunk(n);
+        const int tz = lin_chunk(n, lin_wave_slots(dtype, lin_mode == kLinAlways));
         return lin_tiles(n, tz) * 3 * lin_face_words(tz);
     }
     const int64_t NE = (int64_t)n[0] * n[1] * n[2];

@@ -113,31 +113,36 @@ def test_p1_operator_bytes_follow_the_kernel_switch():
     """p = 1 operators of at most 32768 elements run the sum-factorized kernel and carry its
     per-element skeleton buffer (3 components x 8 element-boundary nodes); larger ones the
     linear-element kernel's tile buffer (8 x 8 column tiles, z chunks as short as keep every
-    tile wavefront resident at two per SIMD, face arrays of 2(tz+1)9 + 2(tz+1)9 + 2 81 words per
-    component).  Host-side accounting only (no GPU call)."""
+    tile wavefront resident: 2048 wavefronts in double precision, 4096 in single, face arrays
+    of 2(tz+1)9 + 2(tz+1)9 + 2 81 words per component).  Host-side accounting only (no GPU
+    call)."""
     capi, lib = _lib()
     from paper_2601_08374_amd import mesh_struct
 
-    def operator_bytes(n):
+    def operator_bytes(n, dtype):
         ms, keep = mesh_struct(syn.BoxMesh(n=n))
-        return lib.pa_bytes_required(C.byref(ms), 1, 0, 0)
+        return lib.pa_bytes_required(C.byref(ms), 1, dtype, 0)
 
-    def tile_words(n):
+    def tile_words(n, slots):
         nxy = ((n[0] + 7) // 8) * ((n[1] + 7) // 8)
         tz = 1
-        while tz < n[2] and nxy * ((n[2] + tz - 1) // tz) > 2048:
+        while tz < n[2] and nxy * ((n[2] + tz - 1) // tz) > slots:
             tz += 1
         tiles = nxy * ((n[2] + tz - 1) // tz)
         return tiles * 3 * (2 * (tz + 1) * 9 * 2 + 2 * 81)
 
-    for n in ((32, 32, 32), (4, 4, 4), (40, 30, 27)):
-        NE = n[0] * n[1] * n[2]
-        assert NE <= 32768
-        assert operator_bytes(n) == NE * 12 * 8 + 24 * NE * 8 + 4096, n
-    for n in ((40, 40, 40), (130, 130, 9), (120, 120, 96), (400, 400, 5)):
-        NE = n[0] * n[1] * n[2]
-        assert NE > 32768
-        assert operator_bytes(n) == NE * 12 * 8 + tile_words(n) * 8 + 4096, n
+    for dtype, w in ((0, 8), (1, 4)):
+        for n in ((32, 32, 32), (4, 4, 4), (40, 30, 27)):
+            NE = n[0] * n[1] * n[2]
+            assert NE <= 32768
+            assert operator_bytes(n, dtype) == NE * 12 * w + 24 * NE * w + 4096, n
+        for n in ((40, 40, 40), (130, 130, 9), (120, 120, 96), (400, 400, 5)):
+            NE = n[0] * n[1] * n[2]
+            assert NE > 32768
+            slots = 2048 if dtype == 0 else 4096
+            assert operator_bytes(n, dtype) == NE * 12 * w + tile_words(n, slots) * w + 4096, (n, dtype)
+    # the two slot counts give different chunks on the sheared box of the benchmark
+    assert tile_words((120, 120, 96), 2048) != tile_words((120, 120, 96), 4096)
 
 
 def test_solve_opts_defaults():

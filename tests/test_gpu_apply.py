@@ -91,8 +91,9 @@ def test_apply_p1_tiles(q, dtype, size):
     """Linear elements, clamped on three faces, with ragged tails on every axis: a small graded
     mesh (at most 32768 elements: the sum-factorized kernel), and two meshes above that size
     (the linear-element kernel) spanning many 8x8-column tiles: 35 x 37 x 27 (one-element
-    z-chunks) and 130 x 130 x 9 (two-element chunks with a one-element last chunk), graded with
-    two spacings per axis (interior, face, edge and corner nodes shared between tiles)."""
+    z-chunks) and 130 x 130 x 27 (four-element chunks with a three-element last chunk in double
+    precision, two-element chunks with a one-element last chunk in single), graded with two
+    spacings per axis (interior, face, edge and corner nodes shared between tiles)."""
     pa = _pa()
     print(f"p=1 tiles size={size} q={q} dtype={dtype}", flush=True)
     A = syn.random_rotation(4) @ syn.SHEAR_A
@@ -101,7 +102,7 @@ def test_apply_p1_tiles(q, dtype, size):
         rng = np.random.default_rng(41)
         lam, mu = rng.uniform(0.2, 3.0, mesh.num_elements), rng.uniform(0.2, 3.0, mesh.num_elements)
     else:
-        n = (35, 37, 27) if size == "tiles" else (130, 130, 9)
+        n = (35, 37, 27) if size == "tiles" else (130, 130, 27)
         L = (1.9, 1.7, 1.2)
         mesh = syn.BoxMesh(n=n, L=L, A=A, grade=[_two_step_grade(n[a], L[a]) for a in range(3)],
                            clamped_faces=0b100101)
