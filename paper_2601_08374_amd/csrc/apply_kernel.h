@@ -247,6 +247,63 @@ inline ApplyTabs<T, D, Q> make_tabs(const Tables& t) {
     return r;
 }
 
+// Tables of the collocated form (affine elements, per-element Lame data, plain tables).
+// J^{-1} and the Lame weights are constant over such an element, so every entry of the
+// reference gradient, of the stress and of Q = sigma J^{-T} is a polynomial of degree at
+// most p in each coordinate and equals its interpolant through the p+1 Gauss-Lobatto nodes
+// per axis.  Substituting that interpolant into the quadrature sums regroups them: the
+// pointwise stage runs at the (p+1)^3 nodes (forward tables: the identity for values and
+// the nodal differentiation matrix l'_i(x_j) for derivatives; unit weights), and the rule
+// enters through the backward tables Mm[j][i] = sum_r w_r l_j(xi_r) l_i(xi_r) and
+// Nm[j][i] = sum_r w_r l_j(xi_r) l'_i(xi_r), built from the tables of the requested q.
+template <typename T, int D>
+inline ApplyTabs<T, D, D> make_colloc_tabs(const Tables& t) {
+    static_assert(!kEvenOdd<D, D>, "the collocated form needs separate backward tables");
+    const int Q = t.q;
+    double Bf[D * D], Gf[D * D], Bt[D * D], Gt[D * D];
+    for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) {
+            Bf[i * D + j] = i == j ? 1.0 : 0.0;
+            double v = 0.0;
+            if (i == j) {
+                for (int m = 0; m < D; ++m)
+                    if (m != i) v += 1.0 / (t.gll[i] - t.gll[m]);
+            } else {
+                double num = 1.0, den = 1.0;
+                for (int m = 0; m < D; ++m) {
+                    if (m == i) continue;
+                    den *= t.gll[i] - t.gll[m];
+                    if (m != j) num *= t.gll[j] - t.gll[m];
+                }
+                v = num / den;
+            }
+            Gf[i * D + j] = v;
+            double mm = 0.0, nm = 0.0;
+            for (int r = 0; r < Q; ++r) {
+                mm += t.w[r] * t.B[j * Q + r] * t.B[i * Q + r];
+                nm += t.w[r] * t.B[j * Q + r] * t.G[i * Q + r];
+            }
+            Bt[j * D + i] = mm;
+            Gt[j * D + i] = nm;
+        }
+    ApplyTabs<T, D, D> r;
+    TabSel<T, D, D>::fill(r.Bf, Bf);
+    TabSel<T, D, D>::fill(r.Gf, Gf);
+    TabSel<T, D, D>::fill(r.bk.Bt, Bt);
+    TabSel<T, D, D>::fill(r.bk.Gt, Gt);
+    for (int k = 0; k < D; ++k) {
+        r.w[k] = T(1);
+        r.x[k] = (T)t.gll[k];
+    }
+    return r;
+}
+
+// Degrees whose affine per-element apply runs in the collocated form: those whose
+// (p+1) x (p+1) tables are plain (the even-odd kernels read their backward tables from the
+// forward ones).
+template <int P>
+constexpr bool kCollocated = !kEvenOdd<P + 1, P + 1>;
+
 // ---------------------------------------------------------------- skeleton numbering
 // Element-boundary ("skeleton") local nodes (some index 0 or p), numbered in
 // lexicographic (iz, iy, ix) order: full layers iz = 0 and iz = p hold D*D nodes,
@@ -959,10 +1016,9 @@ pa_uns_gather_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __rest
 }
 
 template <int P, int Q, typename T, int MAT = kMatElemIso, int GEO = kGeoAffine, bool UNS = false>
-int launch_apply_typed(const ApplyLaunch& L) {
+int launch_apply_tabs(const ApplyLaunch& L, const ApplyTabs<T, P + 1, Q>& tab) {
     using C = ApplyCfg<P, Q, T>;
     if (L.g.NE == 0 && !UNS) return PA_OK;
-    const ApplyTabs<T, P + 1, Q> tab = make_tabs<T, P + 1, Q>(*L.tab);
     const int nb = (L.g.NE + C::E - 1) / C::E;
     if (nb > 0) {
         hipLaunchKernelGGL((pa_apply_kernel<P, Q, T, MAT, GEO, UNS>), dim3(nb), dim3(C::NT), 0, L.stream,
@@ -985,6 +1041,11 @@ int launch_apply_typed(const ApplyLaunch& L) {
                        (const T*)L.sk, L.g, sn, L.add);
     PA_HIP(hipGetLastError());
     return PA_OK;
+}
+
+template <int P, int Q, typename T, int MAT = kMatElemIso, int GEO = kGeoAffine, bool UNS = false>
+int launch_apply_typed(const ApplyLaunch& L) {
+    return launch_apply_tabs<P, Q, T, MAT, GEO, UNS>(L, make_tabs<T, P + 1, Q>(*L.tab));
 }
 
 // Per-point and anisotropic material forms (q = p + 2 only).
@@ -1025,6 +1086,12 @@ int launch_apply_p(const ApplyLaunch& L, int q_off, int dtype) {
     if (L.kmap) return launch_apply_unstructured<P>(L, q_off, dtype);
     if (L.geo != PA_GEOM_AFFINE) return launch_apply_geometry<P>(L, q_off, dtype);
     if (L.mat != PA_MAT_ELEM_ISO) return launch_apply_material<P>(L, q_off, dtype);
+    if constexpr (kCollocated<P>) {
+        // the sums of the requested rule (any q the tables were built for), collocated
+        if (q_off < 0 || q_off > 2) return fail(PA_EUNSUPPORTED, "q = p+1+%d not built", q_off);
+        if (dtype == PA_F64) return launch_apply_tabs<P, P + 1, double>(L, make_colloc_tabs<double, P + 1>(*L.tab));
+        return launch_apply_tabs<P, P + 1, float>(L, make_colloc_tabs<float, P + 1>(*L.tab));
+    }
     if (dtype == PA_F64) {
         switch (q_off) {
             case 0: return launch_apply_typed<P, P + 1, double>(L);
