@@ -198,32 +198,40 @@ struct TabSel<T, NI, NO, false> {
     static void fill(type& t, const double* M) { fill_direct<T, NI, NO>(t, M); }
 };
 
-// Backward tables: plain transposed tables below p = 4; none in the even-odd range,
-// where the backward sweeps read the forward tables transposed (EOT).
-template <typename T, int D, int Q, bool EO = kEvenOdd<D, Q>>
+// Backward tables: plain transposed tables below p = 4; in the even-odd range none (the
+// backward sweeps read the forward tables transposed, EOT), except in the collocated form
+// (COL), whose backward matrices differ from the forward ones: there they are even-odd
+// tables of their own, stored node-major like a forward table and read through EOT.
+template <typename T, int D, int Q, bool EO = kEvenOdd<D, Q>, bool COL = false>
 struct BackTabs {
     typename TabSel<T, Q, D>::type Bt, Gt;   // quadrature (Q) -> nodal (D)
 };
 template <typename T, int D, int Q>
-struct BackTabs<T, D, Q, true> {};
-
+struct BackTabs<T, D, Q, true, false> {};
 template <typename T, int D, int Q>
+struct BackTabs<T, D, Q, true, true> {
+    EOTab<T, D, Q> Bb, Gb;   // node-major: Bb[i][j] = the weight of point j's value at node i
+};
+
+template <typename T, int D, int Q, bool COL = false>
 struct ApplyTabs {
     typename TabSel<T, D, Q>::type Bf, Gf;   // forward: nodal (D) -> quadrature (Q)
-    BackTabs<T, D, Q> bk;
+    BackTabs<T, D, Q, kEvenOdd<D, Q>, COL> bk;
     T w[Q];
     T x[Q];   // Gauss-Legendre points on [0,1] (trilinear geometry)
 };
 
 // Backward operands B^T and G^T of the apply tables.
-template <typename T, int D, int Q>
-__device__ __forceinline__ decltype(auto) back_B(const ApplyTabs<T, D, Q>& t) {
-    if constexpr (kEvenOdd<D, Q>) return EOT<T, Q, D>{t.Bf};
+template <typename T, int D, int Q, bool COL>
+__device__ __forceinline__ decltype(auto) back_B(const ApplyTabs<T, D, Q, COL>& t) {
+    if constexpr (kEvenOdd<D, Q> && COL) return EOT<T, Q, D>{t.bk.Bb};
+    else if constexpr (kEvenOdd<D, Q>) return EOT<T, Q, D>{t.Bf};
     else return (t.bk.Bt);
 }
-template <typename T, int D, int Q>
-__device__ __forceinline__ decltype(auto) back_G(const ApplyTabs<T, D, Q>& t) {
-    if constexpr (kEvenOdd<D, Q>) return EOT<T, Q, D>{t.Gf};
+template <typename T, int D, int Q, bool COL>
+__device__ __forceinline__ decltype(auto) back_G(const ApplyTabs<T, D, Q, COL>& t) {
+    if constexpr (kEvenOdd<D, Q> && COL) return EOT<T, Q, D>{t.bk.Gb};
+    else if constexpr (kEvenOdd<D, Q>) return EOT<T, Q, D>{t.Gf};
     else return (t.bk.Gt);
 }
 
@@ -257,10 +265,11 @@ inline ApplyTabs<T, D, Q> make_tabs(const Tables& t) {
 // enters through the backward tables Mm[j][i] = sum_r w_r l_j(xi_r) l_i(xi_r) and
 // Nm[j][i] = sum_r w_r l_j(xi_r) l'_i(xi_r), built from the tables of the requested q.
 template <typename T, int D>
-inline ApplyTabs<T, D, D> make_colloc_tabs(const Tables& t) {
-    static_assert(!kEvenOdd<D, D>, "the collocated form needs separate backward tables");
+inline ApplyTabs<T, D, D, kEvenOdd<D, D>> make_colloc_tabs(const Tables& t) {
+    constexpr bool EO = kEvenOdd<D, D>;
     const int Q = t.q;
-    double Bf[D * D], Gf[D * D], Bt[D * D], Gt[D * D];
+    // forward [node i][node j]; backward node-major [node i][point j] and point-major [j][i]
+    double Bf[D * D], Gf[D * D], Bn[D * D], Gn[D * D], Bt[D * D], Gt[D * D];
     for (int i = 0; i < D; ++i)
         for (int j = 0; j < D; ++j) {
             Bf[i * D + j] = i == j ? 1.0 : 0.0;
@@ -278,19 +287,26 @@ inline ApplyTabs<T, D, D> make_colloc_tabs(const Tables& t) {
                 v = num / den;
             }
             Gf[i * D + j] = v;
-            double mm = 0.0, nm = 0.0;
+            double mm = 0.0, nm = 0.0;   // Mm[j][i], Nm[j][i]
             for (int r = 0; r < Q; ++r) {
                 mm += t.w[r] * t.B[j * Q + r] * t.B[i * Q + r];
                 nm += t.w[r] * t.B[j * Q + r] * t.G[i * Q + r];
             }
-            Bt[j * D + i] = mm;
-            Gt[j * D + i] = nm;
+            Bt[j * D + i] = Bn[i * D + j] = mm;
+            Gt[j * D + i] = Gn[i * D + j] = nm;
         }
-    ApplyTabs<T, D, D> r;
+    ApplyTabs<T, D, D, EO> r;
     TabSel<T, D, D>::fill(r.Bf, Bf);
     TabSel<T, D, D>::fill(r.Gf, Gf);
-    TabSel<T, D, D>::fill(r.bk.Bt, Bt);
-    TabSel<T, D, D>::fill(r.bk.Gt, Gt);
+    if constexpr (EO) {
+        // node-major, the orientation EOT reads; Mm is symmetric under the mirror i -> D-1-i,
+        // j -> D-1-j and Nm antisymmetric, as B and G are
+        fill_eo<T, D, D>(r.bk.Bb, Bn);
+        fill_eo<T, D, D>(r.bk.Gb, Gn);
+    } else {
+        TabSel<T, D, D>::fill(r.bk.Bt, Bt);
+        TabSel<T, D, D>::fill(r.bk.Gt, Gt);
+    }
     for (int k = 0; k < D; ++k) {
         r.w[k] = T(1);
         r.x[k] = (T)t.gll[k];
@@ -298,11 +314,9 @@ inline ApplyTabs<T, D, D> make_colloc_tabs(const Tables& t) {
     return r;
 }
 
-// Degrees whose affine per-element apply runs in the collocated form: those whose
-// (p+1) x (p+1) tables are plain (the even-odd kernels read their backward tables from the
-// forward ones).
+// Degrees whose affine per-element apply runs in the collocated form.
 template <int P>
-constexpr bool kCollocated = !kEvenOdd<P + 1, P + 1>;
+constexpr bool kCollocated = true;
 
 // ---------------------------------------------------------------- skeleton numbering
 // Element-boundary ("skeleton") local nodes (some index 0 or p), numbered in
@@ -465,10 +479,10 @@ constexpr bool kUnsIdsInLds = sizeof(T) == 8 && (P == 1 || P == 8);
 // nodes go to y directly and element-boundary nodes to the skeleton entry kpos of
 // their (element, slot): entries are stored in the order of the per-node gather lists,
 // so pa_uns_gather_kernel reads each node's contributions as one contiguous run.
-template <int P, int Q, typename T, int MAT = kMatElemIso, int GEO = kGeoAffine, bool UNS = false>
+template <int P, int Q, typename T, int MAT = kMatElemIso, int GEO = kGeoAffine, bool UNS = false, bool COL = false>
 __global__ void __launch_bounds__((ApplyCfg<P, Q, T>::NT))
 pa_apply_kernel(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ sk, const T* __restrict__ ed,
-                const ApplyTabs<T, P + 1, Q> tab, const Geom g, const int add, const T* __restrict__ md,
+                const ApplyTabs<T, P + 1, Q, COL> tab, const Geom g, const int add, const T* __restrict__ md,
                 const T* __restrict__ gd, const int* __restrict__ kmap, const int* __restrict__ kpos) {
     static_assert(GEO == kGeoAffine || MAT == kMatElemIso, "non-affine geometry takes per-element Lame data");
     static_assert(!UNS || GEO == kGeoTri, "unstructured meshes take the recomputed trilinear geometry");
@@ -1015,13 +1029,13 @@ pa_uns_gather_kernel(const T* __restrict__ x, T* __restrict__ y, const T* __rest
     }
 }
 
-template <int P, int Q, typename T, int MAT = kMatElemIso, int GEO = kGeoAffine, bool UNS = false>
-int launch_apply_tabs(const ApplyLaunch& L, const ApplyTabs<T, P + 1, Q>& tab) {
+template <int P, int Q, typename T, int MAT = kMatElemIso, int GEO = kGeoAffine, bool UNS = false, bool COL = false>
+int launch_apply_tabs(const ApplyLaunch& L, const ApplyTabs<T, P + 1, Q, COL>& tab) {
     using C = ApplyCfg<P, Q, T>;
     if (L.g.NE == 0 && !UNS) return PA_OK;
     const int nb = (L.g.NE + C::E - 1) / C::E;
     if (nb > 0) {
-        hipLaunchKernelGGL((pa_apply_kernel<P, Q, T, MAT, GEO, UNS>), dim3(nb), dim3(C::NT), 0, L.stream,
+        hipLaunchKernelGGL((pa_apply_kernel<P, Q, T, MAT, GEO, UNS, COL>), dim3(nb), dim3(C::NT), 0, L.stream,
                            (const T*)L.x, (T*)L.y, (T*)L.sk, (const T*)L.ed, tab, L.g, L.add, (const T*)L.md,
                            (const T*)L.gd, L.kmap, L.kpos);
         PA_HIP(hipGetLastError());
@@ -1089,8 +1103,12 @@ int launch_apply_p(const ApplyLaunch& L, int q_off, int dtype) {
     if constexpr (kCollocated<P>) {
         // the sums of the requested rule (any q the tables were built for), collocated
         if (q_off < 0 || q_off > 2) return fail(PA_EUNSUPPORTED, "q = p+1+%d not built", q_off);
-        if (dtype == PA_F64) return launch_apply_tabs<P, P + 1, double>(L, make_colloc_tabs<double, P + 1>(*L.tab));
-        return launch_apply_tabs<P, P + 1, float>(L, make_colloc_tabs<float, P + 1>(*L.tab));
+        constexpr bool EO = kEvenOdd<P + 1, P + 1>;
+        if (dtype == PA_F64)
+            return launch_apply_tabs<P, P + 1, double, kMatElemIso, kGeoAffine, false, EO>(
+                L, make_colloc_tabs<double, P + 1>(*L.tab));
+        return launch_apply_tabs<P, P + 1, float, kMatElemIso, kGeoAffine, false, EO>(
+            L, make_colloc_tabs<float, P + 1>(*L.tab));
     }
     if (dtype == PA_F64) {
         switch (q_off) {
