@@ -48,10 +48,21 @@ STEP_PS = (1, 2, 4, 6, 8)
 # source hash of the kernels they were taken on, so an edited kernel reports
 # null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("c32ceab031d7bb65", 1, "f64"): 298581760,
-    ("c32ceab031d7bb65", 2, "f64"): 315952950,
-    ("c32ceab031d7bb65", 4, "f64"): 197809853,
-    ("c32ceab031d7bb65", 8, "f64"): 138042068,
+    ("974d3442566f24cd", 1, "f64"): 298462418,
+    ("974d3442566f24cd", 2, "f64"): 316217191,
+    ("974d3442566f24cd", 4, "f64"): 199612569,
+    ("974d3442566f24cd", 8, "f64"): 138049802,
+}
+
+# FP64 FLOPs the fused kernel issues per apply, from rocprofv3 SQ counters of the same
+# runs: 64 lanes x (2 SQ_INSTS_VALU_FMA_F64 + ADD_F64 + MUL_F64) per wave x SQ_WAVES (idle
+# lanes included).  The kernels regroup the paper's sums (closed form at p = 1, collocation
+# at the Gauss-Lobatto nodes above), so they issue fewer FLOPs than F(p) counts.
+MEASURED_ISSUED_FLOPS = {
+    ("974d3442566f24cd", 1, "f64"): 64 * (2 * 1630 + 2174 + 1321) * 2028,
+    ("974d3442566f24cd", 2, "f64"): 64 * (2 * 549 + 18 + 76) * 24686,
+    ("974d3442566f24cd", 4, "f64"): 64 * (2 * 801 + 420 + 126) * 8640,
+    ("974d3442566f24cd", 8, "f64"): 64 * (2 * 2301 + 828 + 226) * 4050,
 }
 
 
@@ -79,7 +90,7 @@ def apply_kernel_names(p: int) -> str:
     """The two kernels of one FP64 apply at degree p (q = p + 2)."""
     if p == 1:
         return "pa_apply_lin_kernel<Q=3,double> + pa_lin_skeleton_kernel<double>"
-    return f"pa_apply_kernel<P={p},Q={p + 2},double> + pa_skeleton_kernel<P={p},double>"
+    return f"pa_apply_kernel<P={p},Q={p + 1},double,collocated> + pa_skeleton_kernel<P={p},double>"
 
 
 def cpu_model() -> str:
@@ -275,7 +286,8 @@ def compact_summary(res: dict) -> dict:
                      "dofs": next(iter(dofs.values())) if len(set(dofs.values())) == 1 else dofs}
     rf = res["roofline"]
     out["roofline"] = {k: rf[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel",
-                                          "flops_per_launch", "algorithmic_bytes_per_launch", "launch_us",
+                                          "flops_per_launch", "issued_flops_per_launch", "frac_issued",
+                                          "algorithmic_bytes_per_launch", "launch_us",
                                           "measured_peak", "frac_measured") if k in rf}
     out["step_per_p_gdofs"] = {str(p): _r(v, 1) for p, v in res["step_per_p_gdofs"].items()}
     cb = res.get("cpu_baseline")
@@ -471,6 +483,10 @@ def main(argv=None):
         roofline.update({"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_F64_TFLOPS,
                          "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_TFLOPS, 4),
                          "hbm_gbs": round(abytes / t_launch / 1e9, 1)})
+
+    issued = MEASURED_ISSUED_FLOPS.get((src_hash, pdom, "f64"))
+    roofline["issued_flops_per_launch"] = issued
+    roofline["frac_issued"] = None if issued is None else round(issued / t_launch / 1e12 / PEAK_F64_TFLOPS, 4)
 
     log("measured ceilings (FMA probe, copy)")
     ceilings = measured_ceilings(torch, dev)

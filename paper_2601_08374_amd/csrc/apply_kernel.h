@@ -375,7 +375,7 @@ struct LdsStrides {
     int RY, RZ, RC, ST;   // Ra: qy, iz, channel, element
 };
 
-// Padded strides for q = p + 2, chosen to minimise bank conflicts of the four access
+// Padded strides, chosen to minimise bank conflicts of the four access
 // patterns (X lines, Y lines on Ua, Y lines on Ra, Z columns): each candidate was
 // scored by the largest number of lanes that share a bank within every group of 16
 // lanes (8-byte words) or 32 lanes (4-byte words), summed over the kernel's LDS
@@ -402,6 +402,14 @@ constexpr LdsStrides lds_strides(int P, int Q, int word) {
             case 6: return {9, 72, 494, 988, 8, 72, 496, 1488};
             case 7: return {9, 72, 576, 1152, 9, 85, 676, 2033};
             case 8: return {13, 117, 1050, 2100, 10, 106, 948, 2844};
+        }
+    }
+    // the collocated form (Q = p + 1) in double precision, chosen the same way; at p = 4 and in
+    // single precision the padded layouts measured no faster than the plain one
+    if (Q == P + 1 && word == 8) {
+        switch (P) {
+            case 2: return {3, 9, 27, 59, 3, 10, 29, 89};
+            case 3: return {5, 20, 79, 158, 4, 20, 76, 228};
         }
     }
     const int D = P + 1, QP = Q | 1;
