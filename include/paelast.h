@@ -74,6 +74,8 @@ extern "C" {
 #define PA_VARIANT_UNFUSED_SF_VOIGT 3 /* as 2 with the Voigt stress form                           */
 #define PA_VARIANT_FUSED_UNSTAGED 4   /* the three passes of 3 fused into one kernel per element,
                                          quadrature-point data staged per element (Alg. 2)     */
+#define PA_VARIANT_FUSED_QUADRATURE 5 /* the fused, register/LDS-staged kernel with its pointwise
+                                         stage at the q^3 Gauss points (no collocation)         */
 
 /* ---- solver modes / stopping tests ----------------------------------------- */
 #define PA_SOLVE_F64 0        /* FP64 PCG with an FP64 V-cycle                                */
@@ -251,8 +253,11 @@ int pa_elast_apply_noalloc(pa_op_t* op, const void* x, void* y, int flags);
  * runs the sum-factorized passes and the Voigt stress in one kernel (macro-kernel
  * fusion, Sec. 4.2, Alg. 2), each workgroup staging its elements' quadrature-point
  * data (9 words per point) in its own part of a work array, then the same
- * assembly -- the production apply adds the slice-wise organisation (Sec. 4.5).
- * For measurement;
+ * assembly -- PA_VARIANT_FUSED_QUADRATURE adds the slice-wise organisation (Sec. 4.5):
+ * the production kernel with the pointwise stage at the q^3 Gauss points, and the
+ * production apply evaluates the same sums in regrouped form (p = 1: closed form from
+ * the rule's centred moments; p >= 2: the pointwise stage at the (p+1)^3 Gauss-Lobatto
+ * nodes, exact for affine elements with per-element Lame data).  For measurement;
  * results equal pa_elast_apply_ex up to rounding.  FP64 operators with q = p+2
  * only (PA_EUNSUPPORTED otherwise); flags 0 or PA_UNCONSTRAINED (y is
  * overwritten).  The first call on an operator allocates its work arrays

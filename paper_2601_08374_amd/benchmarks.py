@@ -261,13 +261,16 @@ def apply_ablation(torch, dev, ps=(1, 2, 4, 8), reps=5):
     """Cumulative ablation of the apply on the sheared box (FP64, q = p+2), in the order of the
     paper's ablation table: unfused dense baseline -> + sum factorization -> + Voigt stress ->
     + fusion into one kernel (quadrature-point data staged per element) -> + the slice-wise
-    organisation (the production apply).  HIP-event time per apply, with rates
+    organisation (registers and LDS tiles; pointwise stage at the q^3 Gauss points) -> + the
+    regrouped sums of the production apply (p = 1 closed form, p >= 2 collocation at the
+    Gauss-Lobatto nodes).  HIP-event time per apply, with rates
     against the FP64 VALU and HBM peaks on the fused operator's FLOP and byte counts."""
     import synthetic as syn
     import paper_2601_08374_amd as pa
     names = [("unfused_dense", pa.capi.PA_VARIANT_UNFUSED_DENSE), ("unfused_sf", pa.capi.PA_VARIANT_UNFUSED_SF),
              ("unfused_sf_voigt", pa.capi.PA_VARIANT_UNFUSED_SF_VOIGT),
-             ("fused_unstaged", pa.capi.PA_VARIANT_FUSED_UNSTAGED), ("fused", pa.capi.PA_VARIANT_FUSED)]
+             ("fused_unstaged", pa.capi.PA_VARIANT_FUSED_UNSTAGED),
+             ("fused_quadrature", pa.capi.PA_VARIANT_FUSED_QUADRATURE), ("fused", pa.capi.PA_VARIANT_FUSED)]
     out = {"workload": "sheared box (~4.2M dofs), FP64, q=p+2, two materials; mean of "
                        f"{reps} applies after one warm-up, HIP events"}
     stream = torch.cuda.current_stream()

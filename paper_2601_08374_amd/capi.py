@@ -31,6 +31,7 @@ PA_VARIANT_UNFUSED_DENSE = 1
 PA_VARIANT_UNFUSED_SF = 2
 PA_VARIANT_UNFUSED_SF_VOIGT = 3
 PA_VARIANT_FUSED_UNSTAGED = 4
+PA_VARIANT_FUSED_QUADRATURE = 5
 PA_MAT_ELEM_ISO = 0
 PA_MAT_QP_ISO = 1
 PA_MAT_ANISO = 2

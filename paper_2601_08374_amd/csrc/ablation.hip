@@ -26,6 +26,7 @@
 
 #include <vector>
 
+#include "apply_kernel.h"
 #include "internal.h"
 #include "kernels.h"
 
@@ -495,10 +496,30 @@ int prepare(pa_op* op) {
 
 }  // namespace
 
+// The production fused kernel with its pointwise stage at the q^3 Gauss points (the form
+// before the collocated regrouping).  Its skeleton buffer holds every element's boundary
+// nodes; at p = 1 the operator's own buffer is sized for the linear-element tiles, so a work
+// array (NE q^3 9 words, far more than NE 24) stands in for it.
+template <int P>
+int run_fused_quadrature(pa_op* op, AblationBuffers* b, const Geom& g, const double* x, double* y) {
+    ApplyLaunch L;
+    L.g = g;
+    L.x = x;
+    L.y = y;
+    L.sk = (P == 1 && op->lin) ? (void*)b->qg : op->sk;
+    L.ed = op->ed;
+    L.tab = &op->tab;
+    L.add = 0;
+    L.lin = false;
+    L.stream = op->stream;
+    return launch_apply_typed<P, P + 2, double>(L);
+}
+
 int apply_variant(pa_op* op, const void* x, void* y, int flags, int variant) {
     if (variant == PA_VARIANT_FUSED) return apply_op(op, x, y, flags);
     if (variant != PA_VARIANT_UNFUSED_DENSE && variant != PA_VARIANT_UNFUSED_SF &&
-        variant != PA_VARIANT_UNFUSED_SF_VOIGT && variant != PA_VARIANT_FUSED_UNSTAGED)
+        variant != PA_VARIANT_UNFUSED_SF_VOIGT && variant != PA_VARIANT_FUSED_UNSTAGED &&
+        variant != PA_VARIANT_FUSED_QUADRATURE)
         return fail(PA_EINVAL, "unknown variant %d", variant);
     if (op->dtype != PA_F64) return fail(PA_EUNSUPPORTED, "the unfused variants are FP64 only");
     if (flags & PA_ADD) return fail(PA_EUNSUPPORTED, "the unfused variants overwrite y (no PA_ADD)");
@@ -509,6 +530,20 @@ int apply_variant(pa_op* op, const void* x, void* y, int flags, int variant) {
     const double* xd = (const double*)x;
     double* yd = (double*)y;
     AblationBuffers* b = op->abl;
+    if (variant == PA_VARIANT_FUSED_QUADRATURE) {
+        if (op->q != op->p + 2) return fail(PA_EUNSUPPORTED, "ablation variants are built for q = p + 2 only");
+        switch (op->p) {
+            case 1: return run_fused_quadrature<1>(op, b, g, xd, yd);
+            case 2: return run_fused_quadrature<2>(op, b, g, xd, yd);
+            case 3: return run_fused_quadrature<3>(op, b, g, xd, yd);
+            case 4: return run_fused_quadrature<4>(op, b, g, xd, yd);
+            case 5: return run_fused_quadrature<5>(op, b, g, xd, yd);
+            case 6: return run_fused_quadrature<6>(op, b, g, xd, yd);
+            case 7: return run_fused_quadrature<7>(op, b, g, xd, yd);
+            case 8: return run_fused_quadrature<8>(op, b, g, xd, yd);
+        }
+        return fail(PA_EUNSUPPORTED, "p = %d", op->p);
+    }
     switch (op->p) {
         case 1: return run_p<1>(op, b, g, xd, yd, variant);
         case 2: return run_p<2>(op, b, g, xd, yd, variant);

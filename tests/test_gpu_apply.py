@@ -277,11 +277,12 @@ def test_apply_bitwise_reproducible(p, dtype):
 
 
 @pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7, 8])
-@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
 def test_apply_variants_parity(p, variant):
     """The earlier ablation forms (dense or sum-factorized gradient/action passes, full-tensor or
-    Voigt stress, unfused or fused with the quadrature-point data staged per element) compute the
-    same operator: FP64 oracle parity, constrained and unconstrained."""
+    Voigt stress, unfused or fused with the quadrature-point data staged per element, the staged
+    kernel at the q^3 Gauss points) compute the same operator: FP64 oracle parity, constrained
+    and unconstrained."""
     pa = _pa()
     print(f"apply variant {variant} p={p}", flush=True)
     mesh = _case_mesh(p, seed=p)
@@ -297,6 +298,31 @@ def test_apply_variants_parity(p, variant):
         y = op.apply_variant(xt, variant=variant, flags=flags)
         torch.cuda.synchronize()
         assert _rel(y.cpu().numpy(), ref) <= TOL[0], (flags, _rel(y.cpu().numpy(), ref))
+
+
+def test_apply_variant_quadrature_p1_tile_mesh():
+    """The staged quadrature-form variant on a p = 1 operator whose production apply runs the
+    linear-element kernel (more than 32768 elements; its skeleton buffer is sized for the lane
+    tiles, so the variant takes a work array of its own): FP64 oracle parity, and the
+    production apply is unchanged after it."""
+    pa = _pa()
+    n = (35, 37, 27)
+    L = (1.9, 1.7, 1.2)
+    mesh = syn.BoxMesh(n=n, L=L, A=syn.SHEAR_A, grade=[_two_step_grade(n[a], L[a]) for a in range(3)],
+                       clamped_faces=0b100101)
+    lam, mu = syn.two_material_lame(mesh.num_elements, seed=8)
+    x = syn.uniform_vector(mesh.num_dofs(1), seed=9)
+    op_ref = elasticity.Operator(mesh, 1, 3, lam, mu)
+    op = pa.Operator(mesh, 1, lam, mu, q=3, dtype=pa.PA_F64)
+    xt = torch.tensor(x, dtype=torch.float64, device="cuda")
+    for flags, constrained in ((0, True), (1, False)):
+        ref = op_ref.apply(x, constrained=constrained)
+        y = op.apply_variant(xt, variant=pa.capi.PA_VARIANT_FUSED_QUADRATURE, flags=flags)
+        torch.cuda.synchronize()
+        assert _rel(y.cpu().numpy(), ref) <= TOL[0], (flags, _rel(y.cpu().numpy(), ref))
+        yp = op.apply(xt, flags=flags)
+        torch.cuda.synchronize()
+        assert _rel(yp.cpu().numpy(), ref) <= TOL[0], (flags, _rel(yp.cpu().numpy(), ref))
 
 
 def test_apply_variant_errors():
