@@ -221,7 +221,13 @@ int64_t pa_bytes_required(const pa_mesh_t* m, int p, int dtype, int with_solver)
  * J^{-T}), forms the Voigt stress with the weighted Lame parameters (eq. 7 and
  * Sec. 4.5), reconstructs Q = sigma J^{-T} (Sec. 4.5, backward
  * reconstruction), contracts back with the transposed sweeps (Sec. 4.5) and
- * scatter-adds (G^T).  x, y: device arrays of N elements of the op's dtype;
+ * scatter-adds (G^T).  On affine elements with per-element Lame parameters the
+ * same sums of the q-point rule are evaluated regrouped: at p >= 2 the pointwise
+ * stage runs at the (p+1)^3 Gauss-Lobatto nodes, where the gradient, the stress and
+ * Q are exactly their polynomial interpolants, and the rule enters through its
+ * 1D mass matrices; at p = 1 a closed form from the rule's centred moments.  The
+ * results equal the point-by-point sums up to rounding.
+ * x, y: device arrays of N elements of the op's dtype;
  * x is not modified; x == y is PA_EINVAL.  With clamped faces this is the
  * constrained operator: clamped entries of x are treated as zero and y equals
  * x on them (identity rows and columns).  No allocation. */
