@@ -145,6 +145,22 @@ def test_p1_operator_bytes_follow_the_kernel_switch():
     assert tile_words((120, 120, 96), 2048) != tile_words((120, 120, 96), 4096)
 
 
+def test_binding_constants_match_the_header():
+    """Every integer constant include/paelast.h defines has the same value in the ctypes
+    binding (host-side check, no GPU)."""
+    from paper_2601_08374_amd import capi
+    hdr = open(os.path.join(ROOT, "include", "paelast.h")).read()
+    defs = {}
+    for name, val in re.findall(r"^#define\s+(PA_\w+)\s+\(?(-?\d+)u?\)?", hdr, flags=re.M):
+        defs[name] = int(val)
+    assert "PA_VARIANT_FUSED_QUADRATURE" in defs and len(defs) >= 25
+    for name, val in defs.items():
+        if name == "PA_NOALLOC_SCRATCH_BYTES":
+            continue   # (64u << 20): not a plain integer literal
+        assert hasattr(capi, name), name
+        assert getattr(capi, name) == val, (name, getattr(capi, name), val)
+
+
 def test_solve_opts_defaults():
     capi, lib = _lib()
     o = capi.pa_solve_opts_t()
