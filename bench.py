@@ -14,7 +14,9 @@ from HBM rather than the 256 MB last-level cache.
 Printed: one short JSON line (the last line of stdout) with value = aggregate
 FP64 apply throughput over the step (total dofs / wall time, GDoF/s), the
 roofline of the dominant kernel (HIP-event timing of its launches inside the
-timed region), the FP64 CPU oracle timed on a bounded sample, the per-p
+timed region; p = 1 against the HBM roof, p >= 2 against the FP64 VALU roof in
+the paper's FLOPs, with the FLOPs the regrouped kernels actually issue beside
+them), the FP64 CPU oracle timed on a bounded sample, the per-p
 FP64/FP32 apply sweep for p = 1..8 and brief solve and serving figures.  The
 full results (sweep rates, ablation, material/geometry/unstructured forms,
 solves, serving) go to the --detail file.
